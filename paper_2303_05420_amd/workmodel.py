@@ -1,0 +1,42 @@
+"""Work model of the Myrtle NNGP: how many covariance entries each pair of
+images carries through the network, and the fixed flop count per entry used
+to express throughput as a fraction of the FP32 vector peak.
+
+Pure Python; loads no native code.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+# Fixed op model (FMA = 2 flops, sqrt = 1 flop): per entry and conv+ReLU layer,
+# 6 flops for the separable 3x3 box sum and 24 for the ReLU arc-cosine map.
+FLOPS_PER_ENTRY_LAYER = 30
+FLOPS_PER_SEED_ENTRY_PER_CHANNEL = 2
+FLOPS_PER_POOLED_ENTRY = 1
+
+
+def stage_sizes(hw: int, n_stages: int):
+    return [hw >> s for s in range(n_stages)]
+
+
+def entry_layers_per_pair(hw: int, depth: Sequence[int]) -> int:
+    """Sum over conv+ReLU layers of the (h w)^2 pair-covariance entries."""
+    return sum(d * (n ** 4) for n, d in zip(stage_sizes(hw, len(depth)), depth))
+
+
+def flops_per_pair(hw: int, c: int, depth: Sequence[int]) -> int:
+    n = stage_sizes(hw, len(depth))
+    f = FLOPS_PER_ENTRY_LAYER * entry_layers_per_pair(hw, depth)
+    f += FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c * n[0] ** 4
+    # every entry leaving a stage is added once into a pooled (or global) sum
+    f += FLOPS_PER_POOLED_ENTRY * sum(k ** 4 for k in n)
+    return f
+
+
+def kernel_storage_bytes(n_examples: int, bytes_per_entry: int = 8) -> float:
+    """Upper triangle of an n x n kernel."""
+    return n_examples * n_examples / 2 * bytes_per_entry
+
+
+def upper_triangle_blocks(n_examples: int, block: int) -> float:
+    return (n_examples / block) ** 2 / 2

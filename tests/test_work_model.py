@@ -1,0 +1,39 @@
+"""The work model reproduces the size/cost figures the paper states
+(tests/golden/paper_scale_figures.txt)."""
+import os
+
+from paper_2303_05420_amd import workmodel
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_scale_figures.txt")
+
+
+def _gold():
+    out = {}
+    for line in open(GOLD):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, v = line.split()[:2]
+        out[k] = v
+    return out
+
+
+def test_storage_and_blocks():
+    g = _gold()
+    n = int(g["largest_kernel_examples"])
+    assert abs(workmodel.kernel_storage_bytes(n) / float(g["largest_kernel_bytes"]) - 1) < 0.01
+    assert abs(workmodel.upper_triangle_blocks(n, int(g["block_side"])) / float(g["largest_kernel_blocks"]) - 1) < 0.01
+
+
+def test_pooling_kernel_cost_grows_with_pixels_squared():
+    g = _gold()
+    # one conv+ReLU layer at full resolution: entries per pair = (h w)^2
+    r = workmodel.entry_layers_per_pair(224, [1]) / workmodel.entry_layers_per_pair(32, [1])
+    assert r == int(g["pool_kernel_cost_ratio"])
+
+
+def test_myrtle10_counts():
+    g = _gold()
+    depth = [int(v) for v in g["myrtle10_conv_per_stage"].split(",")]
+    assert workmodel.entry_layers_per_pair(32, depth) == 3 * (32 ** 4 + 16 ** 4 + 8 ** 4) == 3354624
+    assert workmodel.entry_layers_per_pair(8, [2, 1, 1]) == 8464
