@@ -1,0 +1,194 @@
+"""Benchmark: Myrtle-10 NNGP Gram block (32x32x3 images, 4096 x 4096) on one
+MI355X through libnk.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one nk_myrtle_nngp call on the whole block (variance tables, the
+three fused stage kernels, readout and block write) with the images already
+in device memory.  Prints one JSON line; see the design doc for the fields.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Myrtle-10 NNGP kernel entries/s at 32x32x3; fwd+bwd pairs/s; %FP32 VALU peak"
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA, 64 lanes)
+PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_pmc.json")
+STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage.hip")
+
+
+def _args():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=4096, help="block side (the headline workload is 4096)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=32, help="side of the oracle sample sub-block")
+    p.add_argument("--copy-calib-mib", type=int, default=0,
+                   help="also run a plain device copy of this many MiB (counter calibration runs)")
+    return p.parse_args()
+
+
+def _src_hash(path: str) -> str:
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def _traffic(stage_launch_pairs: int):
+    """HBM bytes per stage-1 launch from the committed counter summary, or None
+    when there is none or the kernel source changed since it was taken."""
+    try:
+        d = json.load(open(PMC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("stage_src_sha256_16") != _src_hash(STAGE_SRC):
+        return None
+    per_pair = d.get("hbm_bytes_per_pair")
+    if per_pair is None:
+        return None
+    return float(per_pair) * stage_launch_pairs
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+              "kernel blocks shard across GPUs without communication, see DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2303_05420_amd import _lib, ops, workmodel
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    w = synth.WORKLOADS["myrtle10_32x32_4096"]
+    n = a.n
+    depth = w["depth"]
+    hw = 32
+    x1n = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][0])
+    x2n = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][1])
+    x1 = torch.from_numpy(x1n).cuda()
+    x2 = torch.from_numpy(x2n).cuda()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    cfg = _lib.myrtle_cfg(hw, 3, depth, w["sigma_w2"], w["sigma_b2"])
+    ws = ops.workspace(ops.workspace_size(_lib.NK_OP_MYRTLE, cfg, n, n), x1.device)
+
+    def step():
+        ops.myrtle_nngp(x1, x2, depth, w["sigma_w2"], w["sigma_b2"], out=out, ws=ws)
+
+    for i in range(a.warmup):
+        step()
+        print(f"warmup step {i + 1}/{a.warmup} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(a.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / a.steps
+    print(f"timed {a.steps} step(s): {ms_step:.1f} ms/step (wall {wall:.1f} s)", file=sys.stderr, flush=True)
+
+    if a.copy_calib_mib:
+        src = torch.ones(a.copy_calib_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    pairs = n * n
+    value = pairs / (ms_step / 1e3)
+
+    # roofline of the dominant kernel (stage 1: seed + 3 conv/ReLU layers at 32x32 + pool)
+    st1 = prof.get(f"myrtle_stage1_n{hw}")
+    roof = None
+    if st1:
+        launches, tot_ms = st1
+        launches_per_step = launches / a.steps
+        pairs_per_launch = pairs / launches_per_step
+        flop_pair_st1 = (workmodel.FLOPS_PER_ENTRY_LAYER * depth[0] * hw ** 4
+                         + workmodel.FLOPS_PER_SEED_ENTRY_PER_CHANNEL * 3 * hw ** 4
+                         + workmodel.FLOPS_PER_POOLED_ENTRY * hw ** 4)
+        avg_s = tot_ms / launches / 1e3
+        achieved = flop_pair_st1 * pairs_per_launch / avg_s / 1e12
+        traffic = _traffic(int(pairs_per_launch))
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": traffic, "kernel": f"myrtle_stage1_n{hw}",
+                "avg_launch_ms": round(tot_ms / launches, 3), "pairs_per_launch": int(pairs_per_launch)}
+    flops_pair = workmodel.flops_per_pair(hw, 3, depth)
+    whole = flops_pair * pairs / (ms_step / 1e3) / 1e12
+
+    cpu = None
+    parity = None
+    if not a.no_cpu_baseline:
+        import oracle
+
+        m = min(a.cpu_sample, n)
+        cores = min(16, len(os.sched_getaffinity(0)))
+        net = oracle.Myrtle(depth, w["sigma_w2"], w["sigma_b2"])
+        pa, pb = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+        plist = np.stack([pa.ravel(), pb.ravel()], 1)
+        t = time.perf_counter()
+        q1, d1 = oracle.myrtle_self(x1n[:m], net, cores)
+        q2, d2 = oracle.myrtle_self(x2n[:m], net, cores)
+        kr = oracle.myrtle_pairs(x1n[:m], x2n[:m], plist, net, q1, q2, cores).reshape(m, m)
+        dt = time.perf_counter() - t
+        # self recursions cost one pair each: count them in the work done
+        cpu = {"value": round(m * m / dt, 3), "unit": "entries/s", "cores": cores, "kind": "oracle",
+               "sample": f"{m}x{m} sub-block of the same 4096x4096 Myrtle-10 block ({m * m} entries, plus "
+                         f"{2 * m} self recursions for the variance maps; {dt:.1f} s of wall time, float64)"}
+        kg = out[:m, :m].cpu().numpy()
+        err = float(np.max(np.abs(kg - kr) / np.sqrt(np.outer(d1, d2))))
+        parity = {"max_normalised_error": err, "entries": m * m, "tolerance": 2e-5}
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Myrtle-10 NNGP, 32x32x3 correlated-Gaussian images (length scale 3 px), "
+                               f"one {n}x{n} Gram block (x1 != x2), sigma_w2=2, sigma_b2=0",
+                   "n1": n, "n2": n, "depth": list(depth), "pairs": pairs},
+        "model_tflops_whole_step": round(whole, 3),
+        "kernels_ms_per_step": {k: round(v[1] / a.steps, 3) for k, v in prof.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

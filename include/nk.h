@@ -1,0 +1,207 @@
+/*
+ * nk.h -- C ABI of libnk, infinite-width neural-network (NNGP) kernels on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those the paper scales up (Adlam et al. 2023, "Kernel
+ * Regression with Infinite-Width Neural Networks on Millions of Examples"):
+ * entries of the NNGP kernel of the FC3 and Myrtle networks of App. A, one
+ * rectangular block of the Gram matrix per call (the unit each device owns
+ * in the blockwise scheme of Fig. 1), and kernel ridge regression with those
+ * kernels (the linear system of Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named x*, K, dK, dx*, Y, pred, ws are DEVICE pointers owned by
+ *    the caller; config structs and nk_tile arrays are HOST memory read
+ *    during the call only.  Inputs are never written.
+ *  - Images are float32, NHWC, contiguous: x[((n * H + y) * W + x) * C + c].
+ *  - K blocks are float32 row-major with leading dimension ldk (elements):
+ *    K[a * ldk + b] = k(x1[a], x2[b]).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *    is asynchronous unless stated otherwise; device faults surface at the
+ *    caller's next synchronisation.  The call returns once the work is
+ *    enqueued.
+ *  - `ws` is caller-owned device scratch of at least nk_workspace_size()
+ *    bytes (256-byte aligned).  Its contents are undefined on return and it
+ *    must not be reused by another call until the stream has passed this
+ *    call's work.
+ *  - Outputs are fully overwritten; nothing accumulates into them.
+ *  - Symmetric blocks: x1 == x2 and n1 == n2 selects the upper-triangle
+ *    path (each unordered pair is computed once and mirrored).
+ *  - Return codes: NK_OK on success, otherwise a negative code; no
+ *    exception crosses the ABI; nk_last_error() holds a message (thread
+ *    local) for the last failing call of the calling thread.
+ *  - Thread safety: calls on different streams with different workspaces
+ *    may run concurrently.
+ */
+#ifndef NK_H
+#define NK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NK_OK = 0,
+  NK_EINVAL = -1,       /* invalid argument (null pointer, bad size, ldk < n2, workspace too small, ...) */
+  NK_EUNSUPPORTED = -2, /* valid but unsupported shape (see each config) */
+  NK_EHIP = -3,         /* a HIP runtime call failed; message in nk_last_error() */
+  NK_ENOMEM = -4,       /* host allocation failed */
+  NK_ENOTPD = -5        /* kernel ridge system not positive definite */
+};
+
+/* Operation ids for nk_workspace_size. */
+enum { NK_OP_FC = 0, NK_OP_MYRTLE = 1, NK_OP_MYRTLE_BWD = 2, NK_OP_KRR = 3, NK_OP_MYRTLE_BATCHED = 4 };
+
+/*
+ * Myrtle network (App. A, Myrtle listing): n_stages stages; stage s runs
+ * depth[s] blocks of [3x3 SAME conv, ReLU] at resolution (H >> s) x (W >> s),
+ * stages are separated by 2x2/stride-2 average pools, and the network ends in
+ * a global average pool and a Dense readout.  Conv weights have variance
+ * sigma_w2 / (9 C_in) and biases sigma_b2; the readout has weight variance
+ * sigma_w2 / C_in and bias sigma_b2.  Myrtle-5 = {2,1,1}, Myrtle-7 =
+ * {2,2,2}, Myrtle-10 = {3,3,3}.
+ *
+ * Supported: H == W, H >> (n_stages-1) in {2,4,8,16,32} at every stage
+ * (H in 2..64 a power of two with all stage sizes <= 64), filter == 3,
+ * 1 <= n_stages <= 4, 0 <= depth[s] <= 4 with depth[0] >= 1, 1 <= C <= 16,
+ * sigma_w2 > 0, sigma_b2 >= 0.  Anything else returns NK_EUNSUPPORTED
+ * (or NK_EINVAL for values that define no network).
+ */
+typedef struct {
+  int32_t H, W, C, n_stages;
+  int32_t depth[4];
+  int32_t filter;
+  float sigma_w2, sigma_b2;
+} nk_myrtle_cfg;
+
+/*
+ * Fully connected network (App. A, FC listing): Flatten, `depth` blocks of
+ * [Dense, ReLU], Dense readout; weight variance sigma_w2 / fan_in, bias
+ * sigma_b2.  FC3 = {d = H*W*C, depth = 3}.
+ */
+typedef struct {
+  int32_t d, depth;
+  float sigma_w2, sigma_b2;
+} nk_fc_cfg;
+
+/* One Gram tile for the batched entry point. */
+typedef struct {
+  const float *x1, *x2; /* device, NHWC images */
+  int64_t n1, n2;
+  float* K; /* device, row-major, leading dimension ldk */
+  int64_t ldk;
+} nk_tile;
+
+/*
+ * Workspace bytes needed by an operation.  cfg points at the op's config
+ * struct (nk_fc_cfg for NK_OP_FC, nk_myrtle_cfg for the Myrtle ops, NULL for
+ * NK_OP_KRR).  n1/n2: block sizes (KRR: n1 = n train, n2 = max(m test, c
+ * targets)); for NK_OP_MYRTLE_BATCHED n1 = total distinct images, n2 = total
+ * pairs.  Returns 0 for invalid arguments.
+ */
+size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2);
+
+/*
+ * FC NNGP block: K[a, b] = k_FC(x1[a], x2[b]) with x* (n*, d) float32
+ * row-major.  The first layer's dot products run on MFMA in fp32.
+ */
+int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_fc_cfg* cfg, float* K,
+               int64_t ldk, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Myrtle NNGP block: K[a, b] = k_Myrtle(x1[a], x2[b]) with x* (n*, H, W, C).
+ * Accuracy: float32 arithmetic; |K - K_exact| / sqrt(K(x,x) K(x',x')) is of
+ * order 1e-6 for the networks above.  Deterministic: the same inputs give
+ * bitwise identical K on the same device.
+ */
+int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K,
+                   int64_t ldk, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint of nk_myrtle_nngp: given the cotangent dK (n1 x n2, leading
+ * dimension lddk) of L(K), writes
+ *   dx1 = dL/dx1 (n1, H, W, C), dx2 = dL/dx2 (n2, H, W, C),
+ *   dsigma[0] = dL/dsigma_w2, dsigma[1] = dL/dsigma_b2 (device, 2 floats).
+ * Any of dx1, dx2, dsigma may be NULL (not computed).  For a symmetric
+ * block (x1 == x2, n1 == n2) the full dK is used (entries (a, b) and (b, a)
+ * both contribute) and the gradient for the shared images goes to dx1; dx2
+ * must then be NULL or equal to dx1.  Covariances are recomputed from the
+ * inputs (no state is kept from the forward call).  Gradients use float32
+ * atomics for per-image accumulation, so they are reproducible only up to
+ * float32 rounding order.
+ */
+int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg,
+                            const float* dK, int64_t lddk, float* dx1, float* dx2, float* dsigma, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/*
+ * Kernel ridge regression (the system of Sec. 2, solved directly):
+ *   lambda = ridge_rel * mean(diag(K_train)),
+ *   alpha  = (K_train + lambda I)^{-1} Y,    pred = K_test alpha,
+ * with K_train (n x n, leading dim n), K_test (m x n, leading dim n), Y and
+ * pred (n x c / m x c, row-major) float32 on the device; the factorisation
+ * and solves run in float64.  Synchronises `stream` before returning so it
+ * can report NK_ENOTPD when the Cholesky factorisation meets a non-positive
+ * pivot (pred is then undefined).
+ */
+int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t m, const float* Y, int64_t c,
+                   double ridge_rel, float* pred, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Cotangents of the held-out squared error of kernel ridge regression,
+ *   L = mean((K_ts alpha - Y_t)^2),  alpha = (K_ss + lambda I)^{-1} Y_s,
+ * with lambda given explicitly (held fixed):
+ *   dK_ts = G alpha^T,  dK_ss = -(A^{-1} K_ts^T G) alpha^T,  G = dL/dpred.
+ * K_ss (n x n), K_ts (m x n), Y_s (n x c), Y_t (m x c) float32 device;
+ * dK_ss (n x n), dK_ts (m x n) float32 device outputs; *loss (host double)
+ * receives L.  Float64 inside.  Synchronises `stream`.
+ */
+int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t m, const float* Y_s,
+                        const float* Y_t, int64_t c, double lambda, float* dK_ss, float* dK_ts, double* loss,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Many Myrtle Gram tiles of uneven size in one scheduled pass: the variance
+ * tables of every distinct image are prepared once and the pairs of all
+ * tiles are dealt over one grid in cost order.  Tiles may share image
+ * arrays (the same x pointer) and must not overlap in their K outputs.
+ * If `graph` is non-zero the pass is captured into a hipGraph on first use
+ * and replayed while the tile list, pointers and workspace are unchanged.
+ * Same accuracy and determinism as nk_myrtle_nngp.
+ */
+int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg, void* ws,
+                           size_t ws_bytes, void* stream, int32_t graph);
+
+/*
+ * Kernel timing (tracing).  After nk_profile_enable(1), every launch of the
+ * library's kernels is bracketed by HIP events recorded on the caller's
+ * stream (no host synchronisation).  nk_profile_read() waits for those
+ * events and writes, per kernel kind, the launch count and summed elapsed
+ * milliseconds into out[0 .. max_entries); it returns the number of kinds
+ * (or a negative code) and clears the records when reset != 0.
+ * nk_profile_enable(0) stops recording.  Process-wide; thread safe.
+ */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} nk_profile_entry;
+
+int nk_profile_enable(int on);
+int nk_profile_read(nk_profile_entry* out, int max_entries, int reset);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char* nk_last_error(void);
+
+/* Library version string. */
+const char* nk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NK_H */

@@ -1,0 +1,135 @@
+"""ctypes view of libnk.so (include/nk.h).  Marshalling only: every step of
+the computation runs in the library's HIP kernels.  Loading fails loudly if
+the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnk.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nk.h")
+
+NK_OK = 0
+NK_EINVAL = -1
+NK_EUNSUPPORTED = -2
+NK_EHIP = -3
+NK_ENOMEM = -4
+NK_ENOTPD = -5
+
+NK_OP_FC = 0
+NK_OP_MYRTLE = 1
+NK_OP_MYRTLE_BWD = 2
+NK_OP_KRR = 3
+NK_OP_MYRTLE_BATCHED = 4
+
+
+class MyrtleCfg(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32), ("n_stages", ctypes.c_int32),
+                ("depth", ctypes.c_int32 * 4), ("filter", ctypes.c_int32), ("sigma_w2", ctypes.c_float),
+                ("sigma_b2", ctypes.c_float)]
+
+
+class FcCfg(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("depth", ctypes.c_int32), ("sigma_w2", ctypes.c_float),
+                ("sigma_b2", ctypes.c_float)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("x1", ctypes.c_void_p), ("x2", ctypes.c_void_p), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64),
+                ("K", ctypes.c_void_p), ("ldk", ctypes.c_int64)]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class NKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnk error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2303_05420_amd.build` "
+                           "(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    ci = ctypes.c_int
+    sz = ctypes.c_size_t
+    L.nk_workspace_size.argtypes = [ci, P, i64, i64]
+    L.nk_workspace_size.restype = sz
+    L.nk_fc_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(FcCfg), P, i64, P, sz, P]
+    L.nk_fc_nngp.restype = ci
+    L.nk_myrtle_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, i64, P, sz, P]
+    L.nk_myrtle_nngp.restype = ci
+    L.nk_myrtle_nngp_backward.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, i64, P, P, P, P, sz, P]
+    L.nk_myrtle_nngp_backward.restype = ci
+    L.nk_krr_predict.argtypes = [P, i64, P, i64, P, i64, ctypes.c_double, P, P, sz, P]
+    L.nk_krr_predict.restype = ci
+    L.nk_krr_mse_backward.argtypes = [P, i64, P, i64, P, P, i64, ctypes.c_double, P, P,
+                                      ctypes.POINTER(ctypes.c_double), P, sz, P]
+    L.nk_krr_mse_backward.restype = ci
+    L.nk_myrtle_nngp_batched.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg), P, sz, P, i32]
+    L.nk_myrtle_nngp_batched.restype = ci
+    L.nk_profile_enable.argtypes = [ci]
+    L.nk_profile_enable.restype = ci
+    L.nk_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ci, ci]
+    L.nk_profile_read.restype = ci
+    L.nk_last_error.argtypes = []
+    L.nk_last_error.restype = ctypes.c_char_p
+    L.nk_version.argtypes = []
+    L.nk_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != NK_OK:
+        raise NKError(rc, lib().nk_last_error().decode())
+
+
+def header_functions() -> list[str]:
+    """Names of every function declared in include/nk.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nk_[a-z0-9_]+)\s*\(", txt)))
+
+
+def myrtle_cfg(hw: int, c: int, depth, sigma_w2: float, sigma_b2: float) -> MyrtleCfg:
+    d = list(depth)
+    if len(d) > 4:
+        raise ValueError("at most 4 stages")
+    cfg = MyrtleCfg()
+    cfg.H = cfg.W = int(hw)
+    cfg.C = int(c)
+    cfg.n_stages = len(d)
+    for i in range(4):
+        cfg.depth[i] = int(d[i]) if i < len(d) else 0
+    cfg.filter = 3
+    cfg.sigma_w2 = float(sigma_w2)
+    cfg.sigma_b2 = float(sigma_b2)
+    return cfg
+
+
+def profile_enable(on: bool = True):
+    check(lib().nk_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{kernel kind: (launches, total_ms)} of the launches recorded so far."""
+    buf = (ProfileEntry * 64)()
+    n = lib().nk_profile_read(buf, 64, 1 if reset else 0)
+    if n < 0:
+        check(n)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(min(n, 64))}

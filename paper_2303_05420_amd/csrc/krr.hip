@@ -1,0 +1,224 @@
+// Kernel ridge regression in float64: the linear system of Sec. 2 (the one
+// the paper's preconditioned conjugate gradients solve iteratively), solved
+// here directly by Cholesky factorisation, which is its exact solution.
+//
+//   lambda = ridge_rel mean(diag K_train),  A = K_train + lambda I = L L^T,
+//   alpha = L^{-T} L^{-1} Y,  pred = K_test alpha.
+//
+// Blocked right-looking Cholesky (block NB): factor the diagonal block in LDS,
+// solve the panel below it, update the trailing lower triangle; then copy L^T
+// into the strict upper triangle so the forward substitution reads rows.
+// Substitutions run one workgroup per right-hand side column with the
+// vector in LDS.
+#include "nk_kernels.h"
+
+namespace nk {
+
+constexpr int CH_NB = 64;
+
+__global__ __launch_bounds__(256) void krr_diag_mean_kernel(const float* __restrict__ K, int64_t n, int64_t ld,
+                                                            double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)K[i * ld + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] / (double)n;
+}
+
+// A = K + (ridge_rel * mean) I   (lower triangle and diagonal are what matter)
+__global__ __launch_bounds__(256) void krr_build_kernel(const float* __restrict__ K, int64_t n, const double* mean,
+                                                        double ridge_rel, double lam_abs, double* __restrict__ A,
+                                                        int* __restrict__ info) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) info[0] = 0;
+  if (e >= n * n) return;
+  const int64_t i = e / n, j = e - i * n;
+  double v = (double)K[e];
+  if (i == j) v += ridge_rel >= 0.0 ? ridge_rel * mean[0] : lam_abs;
+  A[e] = v;
+}
+
+// Cholesky of the nb x nb diagonal block at (k, k), in LDS.
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int64_t n, int64_t k, int nb,
+                                                        int* __restrict__ info) {
+  __shared__ double L[CH_NB][CH_NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    L[i][j] = A[(k + i) * n + k + j];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      const double d = L[j][j];
+      if (!(d > 0.0)) {
+        info[0] = 1;
+        L[j][j] = 1.0;
+      } else {
+        L[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double djj = L[j][j];
+    for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] /= djj;
+    __syncthreads();
+    // trailing update of the block (lower part)
+    for (int e = tid; e < (nb - j - 1) * (nb - j - 1); e += 256) {
+      const int i = j + 1 + e / (nb - j - 1), c = j + 1 + e % (nb - j - 1);
+      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    if (j <= i) A[(k + i) * n + k + j] = L[i][j];
+  }
+}
+
+// Panel: rows i >= k + nb: A[i, k:k+nb] <- A[i, k:k+nb] L_kk^{-T}; one thread per row.
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, int nb) {
+  __shared__ double L[CH_NB][CH_NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    L[i][j] = j <= i ? A[(k + i) * n + k + j] : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = k + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x[CH_NB];
+  double* row = A + i * n + k;
+  for (int j = 0; j < nb; ++j) x[j] = row[j];
+  for (int j = 0; j < nb; ++j) {
+    double v = x[j];
+    for (int t = 0; t < j; ++t) v -= x[t] * L[j][t];
+    x[j] = v / L[j][j];
+  }
+  for (int j = 0; j < nb; ++j) row[j] = x[j];
+}
+
+// Trailing update: A[i][j] -= sum_t A[i][k+t] A[j][k+t] for k+nb <= j <= i < n.
+__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A, int64_t n, int64_t k, int nb) {
+  const int64_t base = k + nb;
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  __shared__ double Pi[CH_NB][CH_NB + 1], Pj[CH_NB][CH_NB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * nb; e += 256) {
+    const int r = e / nb, t = e - r * nb;
+    const int64_t gi = base + bi * 64 + r, gj = base + bj * 64 + r;
+    Pi[r][t] = gi < n ? A[gi * n + k + t] : 0.0;
+    Pj[r][t] = gj < n ? A[gj * n + k + t] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    const int64_t gi = base + bi * 64 + r, gj = base + bj * 64 + c;
+    if (gi >= n || gj >= n || gj > gi) continue;
+    double s = 0.0;
+    for (int t = 0; t < nb; ++t) s += Pi[r][t] * Pj[c][t];
+    A[gi * n + gj] -= s;
+  }
+}
+
+// strict upper triangle <- L^T
+__global__ __launch_bounds__(256) void chol_mirror_kernel(double* __restrict__ A, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e / n, j = e - i * n;
+  if (j > i) A[i * n + j] = A[j * n + i];
+}
+
+// Solve L L^T X = B for one column of B per workgroup; B is float (ld = c)
+// or double (ld = c); X written as double (n x c).
+__global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ A, int64_t n,
+                                                          const float* __restrict__ Bf,
+                                                          const double* __restrict__ Bd, int64_t c,
+                                                          double* __restrict__ X) {
+  extern __shared__ double y[];
+  const int64_t col = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int64_t i = tid; i < n; i += nt) y[i] = Bf ? (double)Bf[i * c + col] : Bd[i * c + col];
+  __syncthreads();
+  // forward: L z = y, L[i][t] = A[t][i] (upper copy) for i > t
+  for (int64_t t = 0; t < n; ++t) {
+    const double zt = y[t] / A[t * n + t];
+    __syncthreads();
+    if (tid == 0) y[t] = zt;
+    for (int64_t i = t + 1 + tid; i < n; i += nt) y[i] -= A[t * n + i] * zt;
+    __syncthreads();
+  }
+  // backward: L^T a = z, (L^T)[t][i] = L[i][t]; row t of L is A[t][0..t]
+  for (int64_t t = n - 1; t >= 0; --t) {
+    const double at = y[t] / A[t * n + t];
+    __syncthreads();
+    if (tid == 0) y[t] = at;
+    for (int64_t i = tid; i < t; i += nt) y[i] -= A[t * n + i] * at;
+    __syncthreads();
+  }
+  for (int64_t i = tid; i < n; i += nt) X[i * c + col] = y[i];
+}
+
+// out (m x c, float) = K (m x n, float, leading dim ld) X (n x c, double)
+__global__ __launch_bounds__(256) void krr_matmul_kernel(const float* __restrict__ K, int64_t m, int64_t n,
+                                                         int64_t ld, const double* __restrict__ X, int64_t c,
+                                                         float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * c) return;
+  const int64_t i = e / c, j = e - i * c;
+  double s = 0.0;
+  const float* row = K + i * ld;
+  for (int64_t t = 0; t < n; ++t) s += (double)row[t] * X[t * c + j];
+  out[e] = (float)s;
+}
+
+int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s) {
+  for (int64_t k = 0; k < n; k += CH_NB) {
+    const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, k, nb, info);
+    const int64_t rest = n - k - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(chol_trsm_kernel, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, s, A, n, k, nb);
+      const unsigned nbk = (unsigned)((rest + 63) / 64);
+      hipLaunchKernelGGL(chol_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, A, n, k, nb);
+    }
+  }
+  hipLaunchKernelGGL(chol_mirror_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, A, n);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double* Bd, int64_t c, double* X,
+                      hipStream_t s) {
+  const size_t lds = (size_t)n * sizeof(double);
+  static size_t attr_bytes = 0;
+  if (lds > 64 * 1024 && attr_bytes < lds) {
+    if (hipFuncSetAttribute((const void*)chol_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+      return -3;
+    attr_bytes = lds;
+  }
+  hipLaunchKernelGGL(chol_solve_kernel, dim3((unsigned)c), dim3(1024), (size_t)n * sizeof(double), s, A, n, Bf, Bd,
+                     c, X);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_krr_build(const float* K, int64_t n, double ridge_rel, double lam_abs, double* mean, double* A,
+                     int* info, hipStream_t s) {
+  if (ridge_rel >= 0.0) hipLaunchKernelGGL(krr_diag_mean_kernel, dim3(1), dim3(256), 0, s, K, n, n, mean);
+  hipLaunchKernelGGL(krr_build_kernel, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, s, K, n, mean,
+                     ridge_rel, lam_abs, A, info);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_krr_matmul(const float* K, int64_t m, int64_t n, int64_t ld, const double* X, int64_t c, float* out,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(krr_matmul_kernel, dim3((unsigned)((m * c + 255) / 256)), dim3(256), 0, s, K, m, n, ld, X, c,
+                     out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace nk

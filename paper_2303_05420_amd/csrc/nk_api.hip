@@ -1,0 +1,396 @@
+// Host side of the libnk C ABI (include/nk.h): argument validation,
+// workspace planning and kernel launch sequencing on the caller's stream.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nk.h"
+#include "nk_kernels.h"
+
+using nk::NetDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return NK_OK;
+}
+
+int hip_fail(const char* where) {
+  hipError_t e = hipGetLastError();
+  return fail(NK_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// ---- kernel timing ------------------------------------------------------
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, std::pair<int64_t, double>> g_prof_done;
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+  bool on = false;
+  ProfRec rec;
+  hipStream_t s;
+  ProfScope(const char* name, hipStream_t stream) : s(stream) {
+    {
+      std::lock_guard<std::mutex> g(g_prof_mu);
+      on = g_prof_on;
+    }
+    if (!on) return;
+    rec.name = name;
+    if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess) {
+      on = false;
+      return;
+    }
+    hipEventRecord(rec.start, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEventRecord(rec.stop, s);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_pending.push_back(rec);
+  }
+};
+
+struct Bump {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = (off + 255) & ~(size_t)255;
+    off = o + bytes;
+    return o;
+  }
+};
+
+constexpr int kPairTile = 16;           // images per side of a pair-order tile
+constexpr int64_t kDefaultChunk = 16384;  // pairs per stage pass for workspace queries
+constexpr int64_t kPrepBlocks = 2048;     // images prepared per launch
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
+  if (!c) return fail(NK_EINVAL, "cfg is NULL");
+  if (c->H <= 0 || c->W <= 0 || c->C <= 0 || c->n_stages <= 0)
+    return fail(NK_EINVAL, "H, W, C and n_stages must be positive");
+  if (!(c->sigma_w2 > 0.f) || !(c->sigma_b2 >= 0.f)) return fail(NK_EINVAL, "need sigma_w2 > 0 and sigma_b2 >= 0");
+  if (c->n_stages > NK_MAX_STAGES) return fail(NK_EUNSUPPORTED, "n_stages > %d", NK_MAX_STAGES);
+  for (int s = 0; s < c->n_stages; ++s)
+    if (c->depth[s] < 0) return fail(NK_EINVAL, "negative depth");
+  if (c->filter != 3) return fail(NK_EUNSUPPORTED, "only 3x3 filters are supported (filter = %d)", c->filter);
+  if (c->H != c->W) return fail(NK_EUNSUPPORTED, "only square images are supported");
+  if (c->C > 4) return fail(NK_EUNSUPPORTED, "at most 4 input channels are supported");
+  if (!is_pow2(c->H) || c->H > 32) return fail(NK_EUNSUPPORTED, "H must be a power of two <= 32 (H = %d)", c->H);
+  if ((c->H >> (c->n_stages - 1)) < 2)
+    return fail(NK_EUNSUPPORTED, "the last stage must be at least 2 x 2 (H = %d, %d stages)", c->H, c->n_stages);
+  if (c->depth[0] < 1) return fail(NK_EUNSUPPORTED, "the first stage needs at least one conv layer");
+  for (int s = 0; s < c->n_stages; ++s)
+    if (c->depth[s] > NK_MAX_DEPTH) return fail(NK_EUNSUPPORTED, "depth per stage must be <= %d", NK_MAX_DEPTH);
+  net->hw = c->H;
+  net->C = c->C;
+  net->S = c->n_stages;
+  for (int s = 0; s < NK_MAX_STAGES; ++s) net->depth[s] = s < c->n_stages ? c->depth[s] : 0;
+  net->sw2 = c->sigma_w2;
+  net->sb2 = c->sigma_b2;
+  for (int s = 0; s < net->S; ++s) {
+    const int N = net->hw >> s;
+    const bool seed = s == 0, pool = s + 1 < net->S;
+    if (nk::stage_lds_bytes(N, net->depth[s], pool, seed) > 160 * 1024)
+      return fail(NK_EUNSUPPORTED, "stage %d needs more than 160 KiB of LDS", s);
+  }
+  return NK_OK;
+}
+
+struct MyrtlePlan {
+  size_t tab1 = 0, tab2 = 0, scratch = 0, buf[NK_MAX_STAGES] = {0, 0, 0, 0};
+  size_t total = 0;
+};
+
+MyrtlePlan plan_myrtle(const NetDesc& net, int64_t n1, int64_t n2, bool sym, int64_t chunk) {
+  MyrtlePlan p;
+  Bump b;
+  const size_t tl = (size_t)nk::table_len(net) * sizeof(float2);
+  p.tab1 = b.take(tl * n1);
+  p.tab2 = sym ? p.tab1 : b.take(tl * n2);
+  const int64_t pb = std::min<int64_t>(std::max(n1, n2), kPrepBlocks);
+  p.scratch = b.take((size_t)nk::prep_scratch_doubles(net) * sizeof(double) * pb);
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    p.buf[s] = b.take(n * n * n * n * sizeof(float) * chunk);
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
+int64_t max_chunk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size_t ws_bytes, int64_t npairs) {
+  const size_t fixed = plan_myrtle(net, n1, n2, sym, 0).total;
+  size_t per = 0;
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    per += n * n * n * n * sizeof(float);
+  }
+  if (ws_bytes < fixed + 256 * NK_MAX_STAGES) return 0;
+  if (per == 0) return npairs;
+  int64_t c = (int64_t)((ws_bytes - fixed - 256 * NK_MAX_STAGES) / per);
+  return std::min(c, npairs);
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Myrtle Gram block through the stage kernels (tables already prepared).
+int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym,
+                     const float2* tab1, const float2* tab2, float* K, int64_t ldk, float* const* bufs,
+                     int64_t chunk, hipStream_t stream) {
+  const int64_t npairs = nk::pair_count(n1, n2, sym);
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, npairs - p0);
+    for (int s = 0; s < net.S; ++s) {
+      nk::StageArgs a;
+      memset(&a, 0, sizeof a);
+      a.n1 = n1;
+      a.n2 = n2;
+      a.sym = sym ? 1 : 0;
+      a.T = kPairTile;
+      a.p0 = p0;
+      a.np = np;
+      a.x1 = x1;
+      a.x2 = x2;
+      a.tab1 = tab1;
+      a.tab2 = tab2;
+      a.tablen = nk::table_len(net);
+      a.taboff = nk::table_off(net, s);
+      a.C = net.C;
+      a.D = net.depth[s];
+      a.sb2 = net.sb2;
+      a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      const bool pool = s + 1 < net.S;
+      a.in = s > 0 ? bufs[s] : nullptr;
+      a.out = pool ? bufs[s + 1] : nullptr;
+      a.K = K;
+      a.ldk = ldk;
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", s + 1, net.hw >> s);
+      ProfScope ps(nm, stream);
+      if (nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream)) return hip_fail("stage kernel");
+    }
+  }
+  return NK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nk_last_error(void) { return g_err.c_str(); }
+
+int nk_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return NK_OK;
+}
+
+int nk_profile_read(nk_profile_entry* out, int max_entries, int reset) {
+  std::vector<ProfRec> pend;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    pend.swap(g_prof_pending);
+  }
+  int rc = NK_OK;
+  std::map<std::string, std::pair<int64_t, double>> add;
+  for (auto& r : pend) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+      rc = fail(NK_EHIP, "profile event: %s", hipGetErrorString(hipGetLastError()));
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+    auto& e = add[r.name];
+    e.first += 1;
+    e.second += ms;
+  }
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& kv : add) {
+    auto& e = g_prof_done[kv.first];
+    e.first += kv.second.first;
+    e.second += kv.second.second;
+  }
+  if (rc) return rc;
+  int n = 0;
+  for (auto& kv : g_prof_done) {
+    if (out && n < max_entries) {
+      memset(&out[n], 0, sizeof out[n]);
+      strncpy(out[n].name, kv.first.c_str(), sizeof out[n].name - 1);
+      out[n].launches = kv.second.first;
+      out[n].total_ms = kv.second.second;
+    }
+    ++n;
+  }
+  if (reset) g_prof_done.clear();
+  return n;
+}
+
+const char* nk_version(void) { return "libnk 0.1 (gfx950)"; }
+
+size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
+  if (n1 < 0 || n2 < 0) return 0;
+  switch (op) {
+    case NK_OP_FC: {
+      Bump b;
+      b.take(sizeof(float) * (size_t)n1);
+      b.take(sizeof(float) * (size_t)n2);
+      return b.off + 256;
+    }
+    case NK_OP_MYRTLE: {
+      NetDesc net;
+      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
+      const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
+      return plan_myrtle(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 256 * NK_MAX_STAGES;
+    }
+    case NK_OP_KRR: {
+      Bump b;
+      b.take(sizeof(double) * (size_t)n1 * n1);
+      b.take(sizeof(double) * 2);
+      b.take(sizeof(int) * 4);
+      b.take(sizeof(double) * (size_t)n1 * std::max<int64_t>(n2, 1));
+      b.take(sizeof(double) * (size_t)n1 * std::max<int64_t>(n2, 1));
+      b.take(sizeof(double) * (size_t)std::max<int64_t>(n2, 1) * std::max<int64_t>(n2, 1));
+      return b.off + 256;
+    }
+    default:
+      return 0;
+  }
+}
+
+int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_fc_cfg* cfg, float* K,
+               int64_t ldk, void* ws, size_t ws_bytes, void* stream) {
+  if (!cfg || !x1 || !x2 || !K) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0 || cfg->d <= 0 || cfg->depth < 0) return fail(NK_EINVAL, "sizes must be positive");
+  if (ldk < n2) return fail(NK_EINVAL, "ldk < n2");
+  if (!(cfg->sigma_w2 > 0.f) || !(cfg->sigma_b2 >= 0.f)) return fail(NK_EINVAL, "need sigma_w2 > 0, sigma_b2 >= 0");
+  const size_t need = nk_workspace_size(NK_OP_FC, cfg, n1, n2);
+  if (!ws || ws_bytes < need) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", need);
+  Bump b;
+  float* d1 = at<float>(ws, b.take(sizeof(float) * n1));
+  float* d2 = at<float>(ws, b.take(sizeof(float) * n2));
+  nk::FcArgs a;
+  a.x1 = x1;
+  a.x2 = x2;
+  a.n1 = n1;
+  a.n2 = n2;
+  a.d = cfg->d;
+  a.depth = cfg->depth;
+  a.sw2 = cfg->sigma_w2;
+  a.sb2 = cfg->sigma_b2;
+  a.d1 = d1;
+  a.d2 = d2;
+  a.K = K;
+  a.ldk = ldk;
+  ProfScope ps("fc_nngp", (hipStream_t)stream);
+  if (nk::launch_fc(a, d1, d2, (hipStream_t)stream)) return hip_fail("fc kernel");
+  return ok();
+}
+
+int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K,
+                   int64_t ldk, void* ws, size_t ws_bytes, void* stream) {
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!x1 || !x2 || !K) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0) return fail(NK_EINVAL, "n1 and n2 must be positive");
+  if (ldk < n2) return fail(NK_EINVAL, "ldk < n2");
+  if (!ws) return fail(NK_EINVAL, "workspace is NULL");
+  const bool sym = (x1 == x2) && (n1 == n2);
+  const int64_t npairs = nk::pair_count(n1, n2, sym);
+  const int64_t chunk = max_chunk(net, n1, n2, sym, ws_bytes, npairs);
+  if (chunk < 1) {
+    return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
+                plan_myrtle(net, n1, n2, sym, 1).total + 256 * NK_MAX_STAGES);
+  }
+  const MyrtlePlan p = plan_myrtle(net, n1, n2, sym, chunk);
+  hipStream_t s = (hipStream_t)stream;
+  float2* tab1 = at<float2>(ws, p.tab1);
+  float2* tab2 = at<float2>(ws, p.tab2);
+  double* scratch = at<double>(ws, p.scratch);
+  {
+    ProfScope ps("myrtle_prepare", s);
+    if (nk::launch_prepare(x1, n1, net, tab1, scratch, kPrepBlocks, s)) return hip_fail("prepare kernel");
+    if (!sym && nk::launch_prepare(x2, n2, net, tab2, scratch, kPrepBlocks, s)) return hip_fail("prepare kernel");
+  }
+  float* bufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  for (int st = 1; st < net.S; ++st) bufs[st] = at<float>(ws, p.buf[st]);
+  rc = run_myrtle_pairs(net, x1, n1, x2, n2, sym, tab1, tab2, K, ldk, bufs, chunk, s);
+  if (rc) return rc;
+  return ok();
+}
+
+int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg,
+                            const float* dK, int64_t lddk, float* dx1, float* dx2, float* dsigma, void* ws,
+                            size_t ws_bytes, void* stream) {
+  (void)x1; (void)n1; (void)x2; (void)n2; (void)cfg; (void)dK; (void)lddk; (void)dx1; (void)dx2; (void)dsigma;
+  (void)ws; (void)ws_bytes; (void)stream;
+  return fail(NK_EUNSUPPORTED, "nk_myrtle_nngp_backward is not available in this build");
+}
+
+int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t m, const float* Y, int64_t c,
+                   double ridge_rel, float* pred, void* ws, size_t ws_bytes, void* stream) {
+  if (!K_train || !Y || (m > 0 && (!K_test || !pred))) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || m < 0 || c <= 0) return fail(NK_EINVAL, "need n > 0, m >= 0, c > 0");
+  if (!(ridge_rel >= 0.0)) return fail(NK_EINVAL, "ridge_rel must be >= 0");
+  if (n > 16384) return fail(NK_EUNSUPPORTED, "n > 16384");
+  const size_t need = nk_workspace_size(NK_OP_KRR, nullptr, n, std::max(m, c));
+  if (!ws || ws_bytes < need) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", need);
+  Bump b;
+  double* A = at<double>(ws, b.take(sizeof(double) * n * n));
+  double* mean = at<double>(ws, b.take(sizeof(double) * 2));
+  int* info = at<int>(ws, b.take(sizeof(int) * 4));
+  double* X = at<double>(ws, b.take(sizeof(double) * n * c));
+  hipStream_t s = (hipStream_t)stream;
+  if (nk::launch_krr_build(K_train, n, ridge_rel, 0.0, mean, A, info, s)) return hip_fail("krr build");
+  if (nk::launch_cholesky(A, n, info, s)) return hip_fail("cholesky");
+  if (nk::launch_chol_solve(A, n, Y, nullptr, c, X, s)) return hip_fail("cholesky solve");
+  if (m > 0 && nk::launch_krr_matmul(K_test, m, n, n, X, c, pred, s)) return hip_fail("krr predict");
+  int h_info = 0;
+  if (hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return hip_fail("krr");
+  if (hipStreamSynchronize(s) != hipSuccess) return hip_fail("krr sync");
+  if (h_info) return fail(NK_ENOTPD, "K_train + lambda I is not positive definite");
+  return ok();
+}
+
+int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t m, const float* Y_s,
+                        const float* Y_t, int64_t c, double lambda, float* dK_ss, float* dK_ts, double* loss,
+                        void* ws, size_t ws_bytes, void* stream) {
+  (void)K_ss; (void)n; (void)K_ts; (void)m; (void)Y_s; (void)Y_t; (void)c; (void)lambda; (void)dK_ss;
+  (void)dK_ts; (void)loss; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(NK_EUNSUPPORTED, "nk_krr_mse_backward is not available in this build");
+}
+
+int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg, void* ws,
+                           size_t ws_bytes, void* stream, int32_t graph) {
+  (void)tiles; (void)ntiles; (void)cfg; (void)ws; (void)ws_bytes; (void)stream; (void)graph;
+  return fail(NK_EUNSUPPORTED, "nk_myrtle_nngp_batched is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Shared device/host definitions of libnk (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// ReLU arc-cosine map, normalised: J1(rho) = (sin t + (pi - t) rho) / pi with
+// cos t = rho, written as J1 = rho + u^{3/2} H(u), u = 1 - rho.  H is our own
+// degree-5 weighted-minimax polynomial fit on [0, 1] (gen_relu_poly.py; max
+// relative error of J1 1.5e-8 in exact arithmetic).  Then
+//   E[relu(a) relu(b)] = sqrt(q q') / 2 * J1(s / sqrt(q q'))
+// for (a, b) ~ N(0, [[q, s], [s, q']]).
+#define NK_J1_C0 0.30010318756103516f
+#define NK_J1_C1 0.015035496093332767f
+#define NK_J1_C2 0.002265139250084758f
+#define NK_J1_C3 0.0008933312492445111f
+#define NK_J1_C4 -0.00022516770695801824f
+#define NK_J1_C5 0.00023788731778040528f
+
+#define NK_MAX_STAGES 4
+#define NK_MAX_DEPTH 4
+#define NK_MAX_C 16
+
+namespace nk {
+
+// Network as the kernels see it (square images, 3x3 filters).
+struct NetDesc {
+  int hw;                    // input resolution (H == W)
+  int C;                     // input channels
+  int S;                     // stages
+  int depth[NK_MAX_STAGES];  // conv+ReLU blocks per stage
+  float sw2, sb2;
+};
+
+__host__ __device__ inline int stage_res(const NetDesc& n, int s) { return n.hw >> s; }
+
+// float2 (alpha, beta) entries per image in the variance tables.
+__host__ __device__ inline int table_len(const NetDesc& n) {
+  int t = 0;
+  for (int s = 0; s < n.S; ++s) t += n.depth[s] * stage_res(n, s) * stage_res(n, s);
+  return t;
+}
+__host__ __device__ inline int table_off(const NetDesc& n, int stage) {
+  int t = 0;
+  for (int s = 0; s < stage; ++s) t += n.depth[s] * stage_res(n, s) * stage_res(n, s);
+  return t;
+}
+
+// Pair index -> (a, b) for a block of n1 x n2 (or the upper triangle of
+// n x n when sym), enumerated in T x T image tiles so that consecutive pairs
+// share images.  Tile rows in order, tiles left to right, row-major inside.
+__host__ __device__ inline void pair_of(int64_t p, int64_t n1, int64_t n2, int sym, int T, int64_t* a,
+                                        int64_t* b) {
+  if (!sym) {
+    int64_t ta = p / ((int64_t)T * n2);
+    int64_t rem = p - ta * (int64_t)T * n2;
+    int64_t h = n1 - ta * T;
+    if (h > T) h = T;
+    int64_t tb = rem / (h * T);
+    int64_t rem2 = rem - tb * h * T;
+    int64_t w = n2 - tb * T;
+    if (w > T) w = T;
+    *a = ta * T + rem2 / w;
+    *b = tb * T + rem2 % w;
+    return;
+  }
+  int64_t n = n1;
+  int64_t NT = (n + T - 1) / T;
+  // C(t): pairs before tile row t (all earlier rows are full): t T(T+1)/2 + T (t n - T t (t+1)/2)
+  int64_t lo = 0, hi = NT - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    int64_t c = mid * (int64_t)T * (T + 1) / 2 + (int64_t)T * (mid * n - (int64_t)T * mid * (mid + 1) / 2);
+    if (c <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int64_t ta = lo;
+  int64_t rem = p - (ta * (int64_t)T * (T + 1) / 2 + (int64_t)T * (ta * n - (int64_t)T * ta * (ta + 1) / 2));
+  int64_t r = n - ta * T;
+  if (r > T) r = T;
+  int64_t ndiag = r * (r + 1) / 2;
+  if (rem < ndiag) {
+    // upper triangle of the diagonal tile, row-major
+    int64_t al = 0;
+    while (rem >= r - al) {
+      rem -= r - al;
+      ++al;
+    }
+    *a = ta * T + al;
+    *b = ta * T + al + rem;
+    return;
+  }
+  rem -= ndiag;
+  int64_t tb = ta + 1 + rem / (r * T);
+  int64_t rem3 = rem - (tb - ta - 1) * r * T;
+  int64_t w = n - tb * T;
+  if (w > T) w = T;
+  *a = ta * T + rem3 / w;
+  *b = tb * T + rem3 % w;
+}
+
+__host__ __device__ inline int64_t pair_count(int64_t n1, int64_t n2, int sym) {
+  return sym ? n1 * (n1 + 1) / 2 : n1 * n2;
+}
+
+// Value of lane - 1 / lane + 1 across the whole wave (0 past the ends).
+__device__ __forceinline__ float lane_prev(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_next(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ float relu_poly(float u) {
+  float p = NK_J1_C5;
+  p = __builtin_fmaf(p, u, NK_J1_C4);
+  p = __builtin_fmaf(p, u, NK_J1_C3);
+  p = __builtin_fmaf(p, u, NK_J1_C2);
+  p = __builtin_fmaf(p, u, NK_J1_C1);
+  p = __builtin_fmaf(p, u, NK_J1_C0);
+  return p;
+}
+
+// J1 for rho >= 0 (every ReLU after the first: inputs are sums of
+// non-negative terms).  u is clamped to [0, 1].
+__device__ __forceinline__ float j1_nonneg(float rho) {
+  float u = __builtin_amdgcn_fmed3f(1.0f - rho, 0.0f, 1.0f);
+  float sq = __builtin_amdgcn_sqrtf(u);
+  return __builtin_fmaf(u * sq, relu_poly(u), rho);
+}
+
+// J1 for rho in [-1, 1]: J1(rho) = J1(|rho|) - |rho| for rho < 0.
+__device__ __forceinline__ float j1_signed(float rho) {
+  float u = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(rho), 0.0f, 1.0f);
+  float sq = __builtin_amdgcn_sqrtf(u);
+  return __builtin_fmaf(u * sq, relu_poly(u), __builtin_fmaxf(rho, 0.0f));
+}
+
+// Logical workgroup index with consecutive indices on the same XCD: the
+// dispatcher deals workgroups round-robin over the 8 XCDs, so remap so that
+// each XCD walks one contiguous range of the pair order (shared images stay
+// in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_logical_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
+  const int64_t start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return start + (b >> 3);
+}
+
+}  // namespace nk

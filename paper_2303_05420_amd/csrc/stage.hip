@@ -1,0 +1,337 @@
+// Fused stage kernel of the Myrtle NNGP forward pass.
+//
+// One Myrtle stage at resolution N x N (App. A: depth blocks of [3x3 SAME
+// conv, ReLU], then a 2x2 average pool or, after the last stage, global
+// average pooling and the Dense readout) for a chunk of image pairs.
+//
+// Layout.  A pair carries the covariance S(i, j) over pixel pairs, N^4
+// entries.  A 3x3 conv maps (i, j) -> (i + d, j + d), so it keeps the
+// displacement j - i; we index entries by k = (j - i) mod N per axis and call
+// the N x N entries with one k = (ky, kx) a tile: entry (iy, ix) of tile k is
+// i = (iy, ix), j = ((iy + ky) mod N, (ix + kx) mod N).  Inside a tile the
+// conv is a 3x3 box filter, except across the seam where j wraps (there the
+// two sides are different displacements, k and k - N) and at the tile edge;
+// those neighbour terms are masked to zero, which is exactly the zero padding
+// of the SAME convolution.  Every tile has N^2 entries, so the work is
+// perfectly regular.
+//
+// Mapping.  A tile lives in one N-lane segment of a wave: lane = ix, register
+// r = iy.  Horizontal neighbours come from DPP lane shifts (masked by two
+// per-lane 0/1 factors fixed for the segment's kx), vertical ones from the
+// neighbouring register (masked by a wave-uniform 0/1 factor at the seam
+// row N - ky).  Each segment owns one kx and sweeps ky = 1, 2, ..., N-1, 0.
+//
+// ReLU.  With the per-image tables (alpha, beta) of prepare.hip:
+//   rho = (box + sigma_b2) alpha(i) alpha'(j),   out = beta(i) beta'(j) J1(rho),
+// which is kappa times the ReLU output, kappa the scale of the next linear
+// step; so the next layer's pre-activation is simply box(out) + sigma_b2.
+//
+// Pooling (2x2, stride 2).  Coarse tile K = ((k + a) >> 1) mod N/2 and row
+// I = i >> 1 for fine row i = 2I + a: even ky rows pool in pairs into K = ky/2,
+// odd ky send even rows to (ky - 1)/2 and odd rows to (ky + 1)/2.  The y part
+// is accumulated in registers along the sweep; the x part (neighbouring kx
+// segments) is combined through LDS in a fixed order, and each finished
+// coarse row of tiles is written once to the next stage's input.  All sums
+// have a fixed order, so results are bitwise reproducible.
+#include "nk_kernels.h"
+
+namespace nk {
+
+
+
+template <int N>
+struct KCfg {
+  static constexpr int THREADS = (N * N > 256) ? N * N : 256;
+  static constexpr int PPWG = THREADS / (N * N);
+};
+
+// LDS per pair: [tables x1: D N^2 float2][tables x2, rows twice: 2 D N^2 float2]
+// [pooling row / readout partials][images as float4 (seeding stage only)]
+template <int N>
+__host__ __device__ inline size_t slot_lds_bytes(int D, bool pool, bool seed) {
+  size_t t = (size_t)D * N * N * 8 + (size_t)D * 2 * N * N * 8 + (seed ? (size_t)2 * N * N * 16 : 0);
+  size_t r = pool ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
+  if (r < 16) r = 16;
+  return (t + r + 15) & ~(size_t)15;
+}
+
+// masked 3-tap sum along the lanes of a segment
+__device__ __forceinline__ float hsum3(float x, float mL, float mR) {
+  return (x + lane_prev(x) * mL) + lane_next(x) * mR;
+}
+
+// wave-uniform 0/1 factor (kept in a scalar register)
+__device__ __forceinline__ float uniform_mask(bool zero) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, zero ? 0.f : 1.f)));
+}
+
+// One [3x3 conv, ReLU] layer on a tile held as A[r] (row r, this lane's column).
+template <int N, bool SIGNED, bool BIAS>
+__device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restrict__ c1,
+                                           const float2* __restrict__ c2, int seam, float mL, float mR,
+                                           float sb2) {
+  float hm = 0.f;
+  float h0 = hsum3(A[0], mL, mR);
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    float hp = 0.f;
+    if (r + 1 < N) hp = hsum3(A[r + 1], mL, mR);
+    float v = h0;
+    if (r > 0) v = __builtin_fmaf(uniform_mask(r == seam), hm, v);
+    if (r + 1 < N) v = __builtin_fmaf(uniform_mask(r + 1 == seam), hp, v);
+    if (BIAS) v += sb2;
+    const float2 a = c1[r * N];
+    const float2 b = c2[r * N];
+    const float rho = v * (a.x * b.x);
+    const float J = SIGNED ? j1_signed(rho) : j1_nonneg(rho);
+    A[r] = (a.y * b.y) * J;
+    hm = h0;
+    h0 = hp;
+  }
+}
+
+template <int N, bool SEED, bool POOL, bool BIAS>
+__global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs args) {
+  constexpr int THREADS = KCfg<N>::THREADS, PPWG = KCfg<N>::PPWG;
+  constexpr int H = N / 2;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ int64_t s_pa[PPWG], s_pb[PPWG];
+
+  const int tid = threadIdx.x;
+  const int slot = tid / (N * N);
+  const int within = tid - slot * N * N;
+  const int kx = within / N, ix = within - kx * N;
+  const int D = args.D;
+  const size_t slot_bytes = slot_lds_bytes<N>(D, POOL, SEED);
+  const int TL = D * N * N;
+
+  const int64_t wg = xcd_logical_block();
+  if (tid < PPWG) {
+    int64_t pl = wg * PPWG + tid;
+    if (pl >= args.np) pl = args.np - 1;
+    int64_t a, b;
+    pair_of(args.p0 + pl, args.n1, args.n2, args.sym, args.T, &a, &b);
+    s_pa[tid] = a;
+    s_pb[tid] = b;
+  }
+  __syncthreads();
+  // this stage's (alpha, beta) tables of both images -> LDS; x2's rows twice
+  for (int e = tid; e < PPWG * TL; e += THREADS) {
+    const int s = e / TL, r = e - s * TL;
+    float2* d1 = reinterpret_cast<float2*>(smem + s * slot_bytes);
+    d1[r] = args.tab1[s_pa[s] * args.tablen + args.taboff + r];
+    const float2 v = args.tab2[s_pb[s] * args.tablen + args.taboff + r];
+    const int l = r / (N * N), rr = r - l * N * N;
+    float2* d2 = d1 + TL + l * 2 * N * N;
+    d2[rr] = v;
+    d2[rr + N * N] = v;
+  }
+  if (SEED) {
+    // images as float4 per pixel (channels zero padded to 4)
+    const size_t rb = POOL ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
+    for (int e = tid; e < PPWG * N * N; e += THREADS) {
+      const int s = e / (N * N), px = e - s * (N * N);
+      float4* d = reinterpret_cast<float4*>(smem + s * slot_bytes + (size_t)TL * 24 + (rb < 16 ? 16 : rb));
+      const float* p1 = args.x1 + (s_pa[s] * (int64_t)N * N + px) * args.C;
+      const float* p2 = args.x2 + (s_pb[s] * (int64_t)N * N + px) * args.C;
+      float u[4] = {0.f, 0.f, 0.f, 0.f}, w[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int c = 0; c < args.C && c < 4; ++c) {
+        u[c] = p1[c];
+        w[c] = p2[c];
+      }
+      d[px] = make_float4(u[0], u[1], u[2], u[3]);
+      d[N * N + px] = make_float4(w[0], w[1], w[2], w[3]);
+    }
+  }
+  __syncthreads();
+
+  const int64_t pl = wg * PPWG + slot;
+  const bool valid = pl < args.np;
+  const int64_t pa = s_pa[slot], pb = s_pb[slot];
+  const float2* t1 = reinterpret_cast<const float2*>(smem + slot * slot_bytes);
+  const float2* t2 = t1 + TL;
+  float* red = reinterpret_cast<float*>(smem + slot * slot_bytes + (size_t)TL * 24);
+  const size_t red_bytes = POOL ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
+  const float4* img1 = reinterpret_cast<const float4*>(smem + slot * slot_bytes + (size_t)TL * 24 +
+                                                       (red_bytes < 16 ? 16 : red_bytes));
+  const float4* img2 = img1 + N * N;
+
+  const float mL = (ix >= 1 && ix != N - kx) ? 1.f : 0.f;
+  const float mR = (ix + 1 < N && ix + 1 != N - kx) ? 1.f : 0.f;
+  const int jx = (ix + kx) & (N - 1);
+
+  float acc[H], wrap[H];
+#pragma unroll
+  for (int I = 0; I < H; ++I) acc[I] = wrap[I] = 0.f;
+  double gsum = 0.0;
+
+  const float* inp = nullptr;
+  if (!SEED) inp = args.in + (pl < args.np ? pl : args.np - 1) * (int64_t)N * N * N * N;
+
+  for (int step = 0; step < N; ++step) {
+    const int ky = (step + 1) & (N - 1);
+    const int seam = ky == 0 ? -1 : N - ky;
+    float A[N];
+    if (SEED) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const int jy = (r + ky) & (N - 1);
+        const float4 u = img1[r * N + ix];
+        const float4 w = img2[jy * N + jx];
+        A[r] = args.seed_scale * __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
+      }
+    } else {
+      const float* p = inp + ((int64_t)ky * N + kx) * N * N + ix;
+#pragma unroll
+      for (int r = 0; r < N; ++r) A[r] = p[r * N];
+    }
+    const float2* c1 = t1 + ix;
+    const float2* c2 = t2 + ky * N + jx;
+    int l = 0;
+    if (SEED) {
+      tile_layer<N, true, BIAS>(A, c1, c2, seam, mL, mR, args.sb2);
+      c1 += N * N;
+      c2 += 2 * N * N;
+      l = 1;
+    }
+    for (; l < D; ++l) {
+      tile_layer<N, false, BIAS>(A, c1, c2, seam, mL, mR, args.sb2);
+      c1 += N * N;
+      c2 += 2 * N * N;
+    }
+
+    if (POOL) {
+      bool emit = false;
+      int Ky = 0;
+      if (ky == 1) {
+#pragma unroll
+        for (int I = 0; I < H; ++I) {
+          wrap[I] = A[2 * I];
+          acc[I] = A[2 * I + 1];
+        }
+        if (N == 2) {
+          // one coarse row only: it completes at ky = 0
+        }
+      } else if (ky == 0) {
+#pragma unroll
+        for (int I = 0; I < H; ++I) acc[I] = acc[I] + (A[2 * I] + A[2 * I + 1]) + wrap[I];
+        emit = true;
+        Ky = 0;
+      } else if ((ky & 1) == 0) {
+#pragma unroll
+        for (int I = 0; I < H; ++I) acc[I] = acc[I] + (A[2 * I] + A[2 * I + 1]);
+      } else {
+#pragma unroll
+        for (int I = 0; I < H; ++I) acc[I] = acc[I] + A[2 * I];
+        emit = true;
+        Ky = (ky - 1) >> 1;
+      }
+      if (emit) {
+        // x combine: coarse Kx gets lanes (2I, 2I+1) of kx = 2Kx, lane 2I of
+        // kx = 2Kx + 1 and lane 2I + 1 of kx = 2Kx - 1
+        float s[H];
+#pragma unroll
+        for (int I = 0; I < H; ++I) s[I] = acc[I] + lane_next(acc[I]);
+        if (!(kx & 1) && !(ix & 1)) {
+#pragma unroll
+          for (int I = 0; I < H; ++I) red[((kx >> 1) * H + I) * H + (ix >> 1)] = s[I];
+        }
+        __syncthreads();
+        if ((kx & 1) && !(ix & 1)) {
+#pragma unroll
+          for (int I = 0; I < H; ++I) red[((kx >> 1) * H + I) * H + (ix >> 1)] += acc[I];
+        }
+        __syncthreads();
+        if ((kx & 1) && (ix & 1)) {
+          const int Kx = ((kx + 1) >> 1) & (H - 1);
+#pragma unroll
+          for (int I = 0; I < H; ++I) red[(Kx * H + I) * H + (ix >> 1)] += acc[I];
+        }
+        __syncthreads();
+        if (valid) {
+          float* o = args.out + pl * (int64_t)H * H * H * H + (int64_t)Ky * H * H * H;
+          for (int e = within; e < H * H * H; e += N * N) o[e] = red[e];
+        }
+        __syncthreads();
+        if (ky != 0) {
+#pragma unroll
+          for (int I = 0; I < H; ++I) acc[I] = A[2 * I + 1];
+        }
+      }
+    } else {
+      float ts[N];
+#pragma unroll
+      for (int r = 0; r < N; ++r) ts[r] = A[r];
+#pragma unroll
+      for (int w = N / 2; w >= 1; w >>= 1) {
+#pragma unroll
+        for (int r = 0; r < w; ++r) ts[r] = ts[r] + ts[r + w];
+      }
+      gsum += (double)ts[0];
+    }
+  }
+
+  if (!POOL) {
+    double* part = reinterpret_cast<double*>(red);
+    part[within] = gsum;
+    __syncthreads();
+    if (within == 0 && valid) {
+      double t = 0.0;
+      for (int e = 0; e < N * N; ++e) t += part[e];
+      const float kv = (float)(t + (double)args.sb2);
+      args.K[pa * args.ldk + pb] = kv;
+      if (args.sym && pa != pb) args.K[pb * args.ldk + pa] = kv;
+    }
+  }
+}
+
+template <int N, bool SEED, bool POOL, bool BIAS>
+static int launch_t(const StageArgs& a, hipStream_t stream) {
+  const int64_t nwg = (a.np + KCfg<N>::PPWG - 1) / KCfg<N>::PPWG;
+  const size_t lds = (size_t)KCfg<N>::PPWG * slot_lds_bytes<N>(a.D, POOL, SEED);
+  auto fn = stage_kernel<N, SEED, POOL, BIAS>;
+  if (lds > 64 * 1024) {
+    static size_t attr_bytes = 0;  // per instantiation
+    if (attr_bytes < lds) {
+      if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -3;
+      attr_bytes = lds;
+    }
+  }
+  hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(KCfg<N>::THREADS), lds, stream, a);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int N>
+static int launch_n(const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s) {
+  if (seed) {
+    if (pool) return bias ? launch_t<N, true, true, true>(a, s) : launch_t<N, true, true, false>(a, s);
+    return bias ? launch_t<N, true, false, true>(a, s) : launch_t<N, true, false, false>(a, s);
+  }
+  if (pool) return bias ? launch_t<N, false, true, true>(a, s) : launch_t<N, false, true, false>(a, s);
+  return bias ? launch_t<N, false, false, true>(a, s) : launch_t<N, false, false, false>(a, s);
+}
+
+size_t stage_lds_bytes(int N, int D, bool pool, bool seed) {
+  switch (N) {
+    case 2: return KCfg<2>::PPWG * slot_lds_bytes<2>(D, pool, seed);
+    case 4: return KCfg<4>::PPWG * slot_lds_bytes<4>(D, pool, seed);
+    case 8: return KCfg<8>::PPWG * slot_lds_bytes<8>(D, pool, seed);
+    case 16: return KCfg<16>::PPWG * slot_lds_bytes<16>(D, pool, seed);
+    case 32: return KCfg<32>::PPWG * slot_lds_bytes<32>(D, pool, seed);
+  }
+  return 0;
+}
+
+int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s) {
+  switch (N) {
+    case 2: return launch_n<2>(a, seed, pool, bias, s);
+    case 4: return launch_n<4>(a, seed, pool, bias, s);
+    case 8: return launch_n<8>(a, seed, pool, bias, s);
+    case 16: return launch_n<16>(a, seed, pool, bias, s);
+    case 32: return launch_n<32>(a, seed, pool, bias, s);
+  }
+  return -2;
+}
+
+}  // namespace nk

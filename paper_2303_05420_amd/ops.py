@@ -1,0 +1,116 @@
+"""Python entry points over libnk (include/nk.h).  Tensors must be CUDA
+(HIP) float32 and contiguous; torch provides the device memory and the
+stream, libnk does all of the computation.  Names match the C ABI."""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib
+
+_ws_cache: dict = {}
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_images(x: torch.Tensor, name: str):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 4:
+        raise TypeError(f"{name} must be a contiguous float32 (n, H, W, C) tensor")
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached uint8 device buffer of at least nbytes (grows, never shrinks)."""
+    key = (str(device),)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = None
+        _ws_cache.pop(key, None)
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def release_workspace():
+    _ws_cache.clear()
+
+
+def workspace_size(op: int, cfg, n1: int, n2: int) -> int:
+    ptr = ctypes.byref(cfg) if cfg is not None else None
+    return int(_lib.lib().nk_workspace_size(op, ptr, int(n1), int(n2)))
+
+
+def myrtle_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: Sequence[int], sigma_w2: float = 2.0,
+                sigma_b2: float = 0.0, out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                ldk: int | None = None) -> torch.Tensor:
+    """Myrtle NNGP block K[a, b] = k(x1[a], x2[b]); x2=None means x1 x x1
+    (upper triangle computed once and mirrored)."""
+    _check_images(x1, "x1")
+    sym = x2 is None
+    if sym:
+        x2 = x1
+    else:
+        _check_images(x2, "x2")
+    n1, h, w, c = x1.shape
+    n2 = x2.shape[0]
+    if x2.shape[1:] != x1.shape[1:]:
+        raise ValueError("x1 and x2 image shapes differ")
+    cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
+    if out is None:
+        ld = n2 if ldk is None else ldk
+        out = torch.empty((n1, ld), dtype=torch.float32, device=x1.device)
+    ld = out.stride(0) if ldk is None else ldk
+    if ws is None:
+        need = workspace_size(_lib.NK_OP_MYRTLE, cfg, n1, n2)
+        if need == 0:
+            _lib.check(_lib.lib().nk_myrtle_nngp(None, 0, None, 0, ctypes.byref(cfg), None, 0, None, 0, None))
+        ws = workspace(need, x1.device)
+    rc = _lib.lib().nk_myrtle_nngp(x1.data_ptr(), n1, x2.data_ptr(), n2, ctypes.byref(cfg), out.data_ptr(), ld,
+                                   ws.data_ptr(), ws.numel(), _stream(x1.device))
+    _lib.check(rc)
+    return out[:, :n2] if out.shape[1] != n2 else out
+
+
+def fc_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 3, sigma_w2: float = 2.0,
+            sigma_b2: float = 0.01, out: torch.Tensor | None = None) -> torch.Tensor:
+    """FC NNGP block on the flattened inputs."""
+    if x2 is None:
+        x2 = x1
+    a = x1.reshape(x1.shape[0], -1)
+    b = x2.reshape(x2.shape[0], -1)
+    for t, nm in ((a, "x1"), (b, "x2")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous float32 CUDA tensor")
+    if a.shape[1] != b.shape[1]:
+        raise ValueError("feature sizes differ")
+    cfg = _lib.FcCfg(int(a.shape[1]), int(depth), float(sigma_w2), float(sigma_b2))
+    if out is None:
+        out = torch.empty((a.shape[0], b.shape[0]), dtype=torch.float32, device=a.device)
+    ws = workspace(workspace_size(_lib.NK_OP_FC, cfg, a.shape[0], b.shape[0]), a.device)
+    rc = _lib.lib().nk_fc_nngp(a.data_ptr(), a.shape[0], b.data_ptr(), b.shape[0], ctypes.byref(cfg),
+                               out.data_ptr(), out.stride(0), ws.data_ptr(), ws.numel(), _stream(a.device))
+    _lib.check(rc)
+    return out
+
+
+def krr_predict(k_train: torch.Tensor, k_test: torch.Tensor, y: torch.Tensor, ridge_rel: float) -> torch.Tensor:
+    """pred = K_test (K_train + lambda I)^{-1} Y with lambda = ridge_rel mean diag (float64 inside)."""
+    for t, nm in ((k_train, "k_train"), (k_test, "k_test"), (y, "y")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous float32 CUDA tensor")
+    n = k_train.shape[0]
+    m = k_test.shape[0]
+    c = y.shape[1]
+    if k_train.shape != (n, n) or k_test.shape[1] != n or y.shape[0] != n:
+        raise ValueError("shape mismatch")
+    pred = torch.empty((m, c), dtype=torch.float32, device=k_train.device)
+    ws = workspace(workspace_size(_lib.NK_OP_KRR, None, n, max(m, c)), k_train.device)
+    rc = _lib.lib().nk_krr_predict(k_train.data_ptr(), n, k_test.data_ptr(), m, y.data_ptr(), c, float(ridge_rel),
+                                   pred.data_ptr(), ws.data_ptr(), ws.numel(), _stream(k_train.device))
+    _lib.check(rc)
+    return pred

@@ -37,7 +37,7 @@ def _standardise(x: np.ndarray) -> np.ndarray:
     mean = x.mean(axis=(0, 1, 2), keepdims=True)
     std = x.std(axis=(0, 1, 2), keepdims=True)
     std[std == 0] = 1.0
-    return ((x - mean) / std).astype(np.float32)
+    return np.ascontiguousarray(((x - mean) / std).astype(np.float32))
 
 
 def iid_images(n: int, h: int, w: int, c: int, seed: int) -> np.ndarray:

@@ -1,0 +1,158 @@
+"""GPU parity of the Myrtle NNGP (libnk HIP kernels) against the FP64 oracle.
+
+Metric: max |K_gpu - K_oracle| / sqrt(K(x,x) K(x',x')) <= 2e-5 (float32
+kernels against the float64 recursion)."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_05420_amd import ops
+    return ops
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _norm_err(kg, kr, d1, d2):
+    return float(np.max(np.abs(kg - kr) / np.sqrt(np.outer(d1, d2))))
+
+
+def _check_block(nk, x1, x2, depth, sw2=2.0, sb2=0.0):
+    net = oracle.Myrtle(depth, sw2, sb2)
+    _say(f"block {x1.shape} x {None if x2 is None else x2.shape} depth={depth} sb2={sb2}")
+    kg = nk.myrtle_nngp(_gpu(x1), None if x2 is None else _gpu(x2), depth, sw2, sb2).cpu().numpy()
+    torch.cuda.synchronize()
+    kr = oracle.myrtle_gram(x1, x2, net)
+    _, d1 = oracle.myrtle_self(x1, net)
+    d2 = d1 if x2 is None else oracle.myrtle_self(x2, net)[1]
+    err = _norm_err(kg, kr, d1, d2)
+    _say(f"  normalised error {err:.3e}")
+    assert err <= TOL
+    return kg, kr
+
+
+def test_myrtle5_8x8_full_gram_128(nk):
+    x = synth.iid_images(128, 8, 8, 3, 1001)
+    kg, kr = _check_block(nk, x, None, (2, 1, 1))
+    assert np.array_equal(kg, kg.T)
+
+
+@pytest.mark.parametrize("n1,n2,hw,depth,sb2", [
+    (37, 29, 8, (2, 1, 1), 0.0),
+    (33, 17, 8, (2, 1, 1), 0.05),
+    (9, 11, 16, (1, 2, 1), 0.0),
+    (7, 5, 16, (2, 2, 2), 0.02),
+    (6, 5, 32, (2, 1, 1), 0.0),
+    (3, 4, 32, (3, 3, 3), 0.1),
+])
+def test_myrtle_blocks_ragged(nk, n1, n2, hw, depth, sb2):
+    x1 = synth.correlated_images(n1, hw, hw, 3, 3.0, 11 + n1)
+    x2 = synth.correlated_images(n2, hw, hw, 3, 3.0, 12 + n2)
+    _check_block(nk, x1, x2, depth, 2.0, sb2)
+
+
+@pytest.mark.parametrize("hw,depth,c", [
+    (8, (2,), 3),          # one stage: global pool straight after the first convs
+    (16, (1, 1, 1, 1), 3),  # four stages, last at 2 x 2
+    (8, (2, 0, 1), 3),     # a stage that only pools
+    (8, (1, 1, 1), 1),     # one input channel
+    (4, (1, 1), 4),        # four channels, 4 x 4 images
+    (2, (3,), 2),          # 2 x 2 images
+])
+def test_myrtle_degenerate_networks(nk, hw, depth, c):
+    x1 = synth.iid_images(5, hw, hw, c, 200 + hw)
+    x2 = synth.iid_images(3, hw, hw, c, 300 + hw)
+    _check_block(nk, x1, x2, depth, 1.7, 0.0)
+    _check_block(nk, x1, None, depth, 2.0, 0.03)
+
+
+def test_single_pair_and_leading_dimension(nk):
+    x1 = synth.iid_images(1, 8, 8, 3, 5)
+    x2 = synth.iid_images(1, 8, 8, 3, 6)
+    _check_block(nk, x1, x2, (2, 1, 1))
+    xa = synth.iid_images(4, 8, 8, 3, 7)
+    xb = synth.iid_images(3, 8, 8, 3, 8)
+    out = torch.full((4, 8), -7.0, device="cuda")
+    nk.myrtle_nngp(_gpu(xa), _gpu(xb), (2, 1, 1), out=out, ldk=8)
+    o = out.cpu().numpy()
+    assert np.all(o[:, 3:] == -7.0)
+    kr = oracle.myrtle_gram(xa, xb, oracle.Myrtle((2, 1, 1)))
+    assert np.max(np.abs(o[:, :3] - kr)) <= TOL * np.abs(kr).max()
+
+
+def test_symmetric_path_matches_block_path(nk):
+    """The upper triangle of the symmetric path is the same computation as
+    the block path (bitwise); the block path's lower triangle evaluates
+    k(x_b, x_a) with the images' roles swapped, equal up to rounding."""
+    x = synth.correlated_images(23, 16, 16, 3, 3.0, 41)
+    xg = _gpu(x)
+    ks = nk.myrtle_nngp(xg, None, (2, 1, 1)).cpu().numpy()
+    kb = nk.myrtle_nngp(xg, xg.clone(), (2, 1, 1)).cpu().numpy()
+    iu = np.triu_indices(23)
+    assert np.array_equal(ks[iu], kb[iu])
+    assert np.array_equal(ks, ks.T)
+    assert np.max(np.abs(ks - kb)) <= 1e-6 * np.abs(ks).max()
+
+
+def test_deterministic_and_chunk_independent(nk):
+    from paper_2303_05420_amd import _lib
+    x1 = _gpu(synth.correlated_images(20, 16, 16, 3, 3.0, 51))
+    x2 = _gpu(synth.correlated_images(19, 16, 16, 3, 3.0, 52))
+    depth = (2, 1, 1)
+    a = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+    b = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+    assert np.array_equal(a, b)
+    # a workspace that only holds a few pairs per pass gives the same bits
+    cfg = _lib.myrtle_cfg(16, 3, depth, 2.0, 0.0)
+    fixed = nk.workspace_size(_lib.NK_OP_MYRTLE, cfg, 20, 19) - min(380, 16384) * (8 ** 4 + 4 ** 4) * 4
+    small = torch.empty(fixed + 7 * (8 ** 4 + 4 ** 4) * 4 + 4096, dtype=torch.uint8, device="cuda")
+    c = nk.myrtle_nngp(x1, x2, depth, ws=small).cpu().numpy()
+    assert np.array_equal(a, c)
+
+
+def test_myrtle10_32x32_block4096_sampled(nk):
+    """Myrtle-10 on 32x32x3 correlated images, one 4096 x 4096 block, checked
+    on seeded samples against the oracle."""
+    w = synth.WORKLOADS["myrtle10_32x32_4096"]
+    x1 = synth.correlated_images(w["n1"], 32, 32, 3, w["length"], w["seeds"][0])
+    x2 = synth.correlated_images(w["n2"], 32, 32, 3, w["length"], w["seeds"][1])
+    _say("myrtle10 4096 x 4096 block on GPU")
+    kg = nk.myrtle_nngp(_gpu(x1), _gpu(x2), w["depth"], w["sigma_w2"], w["sigma_b2"]).cpu().numpy()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3003)
+    pairs = np.concatenate([rng.integers(0, 4096, size=(64, 2)),
+                            np.array([[0, 0], [4095, 4095], [0, 4095], [4095, 0], [2048, 17]])])
+    net = oracle.Myrtle(w["depth"], w["sigma_w2"], w["sigma_b2"])
+    _say("oracle on sampled pairs")
+    kr = oracle.myrtle_pairs(x1, x2, pairs, net)
+    ua = np.unique(pairs[:, 0])
+    ub = np.unique(pairs[:, 1])
+    _, da = oracle.myrtle_self(x1[ua], net)
+    _, db = oracle.myrtle_self(x2[ub], net)
+    d1 = dict(zip(ua, da))
+    d2 = dict(zip(ub, db))
+    err = max(abs(kg[a, b] - k) / np.sqrt(d1[a] * d2[b]) for (a, b), k in zip(pairs, kr))
+    _say(f"  normalised error {err:.3e}")
+    assert err <= TOL
+    assert np.all(np.isfinite(kg)) and np.all(kg > 0)
