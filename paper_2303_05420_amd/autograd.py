@@ -1,0 +1,39 @@
+"""torch.autograd.Function over the libnk Myrtle NNGP: the forward calls
+nk_myrtle_nngp, the backward nk_myrtle_nngp_backward (which recomputes the
+covariances from the saved inputs; nothing else is saved)."""
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+from . import ops
+
+
+class MyrtleNNGP(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x1, x2, sigma_w2, sigma_b2, depth: Sequence[int]):
+        sw2 = float(sigma_w2)
+        sb2 = float(sigma_b2)
+        sym = x2 is None
+        K = ops.myrtle_nngp(x1.contiguous(), None if sym else x2.contiguous(), depth, sw2, sb2)
+        ctx.save_for_backward(x1, x1 if sym else x2)
+        ctx.sym = sym
+        ctx.depth = tuple(depth)
+        ctx.sw2, ctx.sb2 = sw2, sb2
+        ctx.sig_is_tensor = (isinstance(sigma_w2, torch.Tensor), isinstance(sigma_b2, torch.Tensor))
+        return K.clone()
+
+    @staticmethod
+    def backward(ctx, gK):
+        x1, x2 = ctx.saved_tensors
+        dx1, dx2, ds = ops.myrtle_nngp_backward(x1.contiguous(), None if ctx.sym else x2.contiguous(),
+                                                gK.contiguous().float(), ctx.depth, ctx.sw2, ctx.sb2)
+        gw = ds[0].to(torch.float32) if ctx.sig_is_tensor[0] else None
+        gb = ds[1].to(torch.float32) if ctx.sig_is_tensor[1] else None
+        return dx1, None if ctx.sym else dx2, gw, gb, None
+
+
+def myrtle_nngp(x1, x2, sigma_w2, sigma_b2, depth):
+    """Differentiable Myrtle NNGP block (x2=None: symmetric block of x1)."""
+    return MyrtleNNGP.apply(x1, x2, sigma_w2, sigma_b2, depth)

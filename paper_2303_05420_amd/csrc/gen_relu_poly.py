@@ -10,7 +10,12 @@ u^{3/2} / J1), using Lawson's iteratively reweighted least squares on 4000
 Chebyshev points, with H evaluated in 40-digit arithmetic.  Negative rho uses
 J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
 
-Run: python gen_relu_poly.py  (prints the coefficients and the fit error).
+The adjoint needs dJ1/drho = (pi - t) / pi with t = acos(rho).  For
+rho = 1 - u, t = sqrt(u) G(u) with G analytic on [0, 1] (G(0) = sqrt 2);
+G is fitted by a degree-6 polynomial minimising the maximum absolute error of
+sqrt(u) G(u) / pi (Lawson again); negative rho uses acos(-r) = pi - acos(r).
+
+Run: python gen_relu_poly.py  (prints the coefficients and the fit errors).
 """
 import mpmath as mp
 import numpy as np
@@ -47,5 +52,32 @@ def main(degree: int = 5, m: int = 4000):
         print(f"#define NK_J1_C{k} {float(ck)!r}f")
 
 
+def main_acos(degree: int = 6, m: int = 3000):
+    mp.mp.dps = 40
+
+    def g(u):
+        u = mp.mpf(u)
+        if u == 0:
+            return mp.sqrt(2)
+        return mp.acos(1 - u) / mp.sqrt(u)
+
+    us = (1 - np.cos(np.pi * (np.arange(m) + 0.5) / m)) / 2
+    us = np.concatenate([[0.0], us, [1.0]])
+    gs = np.array([float(g(u)) for u in us])
+    w = np.sqrt(us) / np.pi
+    v = np.vander(us, degree + 1, increasing=True)
+    lw = np.ones(len(us)) / len(us)
+    for _ in range(400):
+        sw = np.sqrt(lw) * np.maximum(w, 1e-3)
+        c, *_ = np.linalg.lstsq(v * sw[:, None], gs * sw, rcond=None)
+        e = np.abs((v @ c - gs) * w)
+        lw = lw * np.maximum(e, 1e-30)
+        lw /= lw.sum()
+    print(f"max absolute error of dJ1/drho (float64 evaluation): {e.max():.3e}")
+    for k, ck in enumerate(c.astype(np.float32)):
+        print(f"#define NK_ACOS_C{k} {float(ck)!r}f")
+
+
 if __name__ == "__main__":
     main()
+    main_acos()

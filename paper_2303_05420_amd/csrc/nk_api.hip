@@ -143,6 +143,51 @@ MyrtlePlan plan_myrtle(const NetDesc& net, int64_t n1, int64_t n2, bool sym, int
   return p;
 }
 
+constexpr int64_t kPrepBwdBlocks = 256;  // images per self-recursion adjoint launch
+
+struct BwdPlan {
+  size_t tab1 = 0, tab2 = 0, scratch = 0, W1 = 0, W2 = 0, xb1 = 0, xb2 = 0, sums = 0, bscratch = 0;
+  size_t buf[NK_MAX_STAGES] = {0, 0, 0, 0}, gbuf[NK_MAX_STAGES] = {0, 0, 0, 0};
+  size_t total = 0;
+};
+
+BwdPlan plan_bwd(const NetDesc& net, int64_t n1, int64_t n2, bool sym, int64_t chunk) {
+  BwdPlan p;
+  Bump b;
+  const size_t tl = (size_t)nk::table_len(net);
+  const size_t img = (size_t)net.hw * net.hw * net.C;
+  p.tab1 = b.take(tl * sizeof(float2) * n1);
+  p.tab2 = sym ? p.tab1 : b.take(tl * sizeof(float2) * n2);
+  const int64_t pb = std::min<int64_t>(std::max(n1, n2), kPrepBlocks);
+  p.scratch = b.take((size_t)nk::prep_scratch_doubles(net) * sizeof(double) * pb);
+  p.W1 = b.take(tl * sizeof(double) * n1);
+  p.W2 = sym ? p.W1 : b.take(tl * sizeof(double) * n2);
+  p.xb1 = b.take(img * sizeof(double) * n1);
+  p.xb2 = sym ? p.xb1 : b.take(img * sizeof(double) * n2);
+  p.sums = b.take(4 * sizeof(double));
+  const int64_t pbb = std::min<int64_t>(std::max(n1, n2), kPrepBwdBlocks);
+  p.bscratch = b.take((size_t)nk::prep_bwd_scratch_doubles(net) * sizeof(double) * pbb);
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    p.buf[s] = b.take(n * n * n * n * sizeof(float) * chunk);
+    p.gbuf[s] = b.take(n * n * n * n * sizeof(float) * chunk);
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
+int64_t max_chunk_bwd(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size_t ws_bytes, int64_t npairs) {
+  const size_t fixed = plan_bwd(net, n1, n2, sym, 0).total;
+  size_t per = 0;
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    per += 2 * n * n * n * n * sizeof(float);
+  }
+  if (ws_bytes < fixed + 512 * NK_MAX_STAGES) return 0;
+  if (per == 0) return npairs;
+  return std::min((int64_t)((ws_bytes - fixed - 512 * NK_MAX_STAGES) / per), npairs);
+}
+
 int64_t max_chunk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size_t ws_bytes, int64_t npairs) {
   const size_t fixed = plan_myrtle(net, n1, n2, sym, 0).total;
   size_t per = 0;
@@ -269,6 +314,12 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
       const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
       return plan_myrtle(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 256 * NK_MAX_STAGES;
     }
+    case NK_OP_MYRTLE_BWD: {
+      NetDesc net;
+      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
+      const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
+      return plan_bwd(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 512 * NK_MAX_STAGES;
+    }
     case NK_OP_KRR: {
       Bump b;
       b.take(sizeof(double) * (size_t)n1 * n1);
@@ -349,9 +400,97 @@ int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, con
 int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg,
                             const float* dK, int64_t lddk, float* dx1, float* dx2, float* dsigma, void* ws,
                             size_t ws_bytes, void* stream) {
-  (void)x1; (void)n1; (void)x2; (void)n2; (void)cfg; (void)dK; (void)lddk; (void)dx1; (void)dx2; (void)dsigma;
-  (void)ws; (void)ws_bytes; (void)stream;
-  return fail(NK_EUNSUPPORTED, "nk_myrtle_nngp_backward is not available in this build");
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!x1 || !x2 || !dK) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0) return fail(NK_EINVAL, "n1 and n2 must be positive");
+  if (lddk < n2) return fail(NK_EINVAL, "lddk < n2");
+  if (!ws) return fail(NK_EINVAL, "workspace is NULL");
+  const bool sym = (x1 == x2) && (n1 == n2);
+  if (sym && dx2 && dx2 != dx1) return fail(NK_EINVAL, "symmetric block: dx2 must be NULL or equal to dx1");
+  for (int s = 0; s < net.S; ++s)
+    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0, net.C) > 160 * 1024)
+      return fail(NK_EUNSUPPORTED, "adjoint of stage %d needs more than 160 KiB of LDS", s);
+  const int64_t npairs = nk::pair_count(n1, n2, sym);
+  const int64_t chunk = max_chunk_bwd(net, n1, n2, sym, ws_bytes, npairs);
+  if (chunk < 1)
+    return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
+                plan_bwd(net, n1, n2, sym, 1).total + 512 * NK_MAX_STAGES);
+  const BwdPlan p = plan_bwd(net, n1, n2, sym, chunk);
+  hipStream_t s = (hipStream_t)stream;
+  float2* tab1 = at<float2>(ws, p.tab1);
+  float2* tab2 = at<float2>(ws, p.tab2);
+  double* W1 = at<double>(ws, p.W1);
+  double* W2 = at<double>(ws, p.W2);
+  double* xb1 = at<double>(ws, p.xb1);
+  double* xb2 = at<double>(ws, p.xb2);
+  double* sums = at<double>(ws, p.sums);
+  const int tl = nk::table_len(net);
+  const int64_t img = (int64_t)net.hw * net.hw * net.C;
+  {
+    ProfScope ps("myrtle_prepare", s);
+    if (nk::launch_prepare(x1, n1, net, tab1, at<double>(ws, p.scratch), kPrepBlocks, s))
+      return hip_fail("prepare kernel");
+    if (!sym && nk::launch_prepare(x2, n2, net, tab2, at<double>(ws, p.scratch), kPrepBlocks, s))
+      return hip_fail("prepare kernel");
+  }
+  if (nk::launch_zero_f64(W1, n1 * tl, s) || nk::launch_zero_f64(xb1, n1 * img, s) || nk::launch_zero_f64(sums, 4, s))
+    return hip_fail("zero");
+  if (!sym && (nk::launch_zero_f64(W2, n2 * tl, s) || nk::launch_zero_f64(xb2, n2 * img, s))) return hip_fail("zero");
+  float* bufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  float* gbufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  for (int st = 1; st < net.S; ++st) {
+    bufs[st] = at<float>(ws, p.buf[st]);
+    gbufs[st] = at<float>(ws, p.gbuf[st]);
+  }
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, npairs - p0);
+    // forward up to the last stage's input (the checkpoints of the adjoint)
+    for (int st = 0; st + 1 < net.S; ++st) {
+      nk::StageArgs a;
+      memset(&a, 0, sizeof a);
+      a.n1 = n1; a.n2 = n2; a.sym = sym ? 1 : 0; a.T = kPairTile; a.p0 = p0; a.np = np;
+      a.x1 = x1; a.x2 = x2; a.tab1 = tab1; a.tab2 = tab2;
+      a.tablen = tl; a.taboff = nk::table_off(net, st);
+      a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      a.in = st > 0 ? bufs[st] : nullptr;
+      a.out = bufs[st + 1];
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", st + 1, net.hw >> st);
+      ProfScope ps(nm, s);
+      if (nk::launch_stage(net.hw >> st, a, st == 0, true, net.sb2 != 0.f, s)) return hip_fail("stage kernel");
+    }
+    for (int st = net.S - 1; st >= 0; --st) {
+      nk::StageBwdArgs b;
+      memset(&b, 0, sizeof b);
+      b.n1 = n1; b.n2 = n2; b.sym = sym ? 1 : 0; b.T = kPairTile; b.p0 = p0; b.np = np;
+      b.x1 = x1; b.x2 = x2; b.tab1 = tab1; b.tab2 = tab2;
+      b.tablen = tl; b.taboff = nk::table_off(net, st);
+      b.C = net.C; b.D = net.depth[st]; b.sb2 = net.sb2; b.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      b.in = st > 0 ? bufs[st] : nullptr;
+      b.gin = st + 1 < net.S ? gbufs[st + 1] : nullptr;
+      b.gout = st > 0 ? gbufs[st] : nullptr;
+      b.dK = dK; b.lddk = lddk;
+      b.W1 = W1; b.W2 = W2; b.xbar1 = xb1; b.xbar2 = xb2; b.sums = sums;
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d_bwd", st + 1, net.hw >> st);
+      ProfScope ps(nm, s);
+      if (nk::launch_stage_bwd(net.hw >> st, b, st == 0, st + 1 == net.S, net.sb2 != 0.f, s))
+        return hip_fail("adjoint stage kernel");
+    }
+  }
+  {
+    ProfScope ps("myrtle_self_bwd", s);
+    double* bs = at<double>(ws, p.bscratch);
+    if (nk::launch_prepare_bwd(x1, n1, net, W1, tl, xb1, sums, bs, kPrepBwdBlocks, s)) return hip_fail("self adjoint");
+    if (!sym && nk::launch_prepare_bwd(x2, n2, net, W2, tl, xb2, sums, bs, kPrepBwdBlocks, s))
+      return hip_fail("self adjoint");
+  }
+  if (dx1 && nk::launch_cast_grad(xb1, dx1, n1 * img, s)) return hip_fail("cast");
+  if (!sym && dx2 && nk::launch_cast_grad(xb2, dx2, n2 * img, s)) return hip_fail("cast");
+  if (dsigma && nk::launch_finish_sigma(sums, (double)net.sw2, dsigma, s)) return hip_fail("sigma");
+  return ok();
 }
 
 int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t m, const float* Y, int64_t c,

@@ -16,6 +16,16 @@
 #define NK_J1_C4 -0.00022516770695801824f
 #define NK_J1_C5 0.00023788731778040528f
 
+// acos(1 - u) = sqrt(u) G(u); G is our own degree-6 fit on [0, 1]
+// (gen_relu_poly.py; dJ1/drho = 1 - acos(rho)/pi to 2.8e-8).
+#define NK_ACOS_C0 1.414214849472046f
+#define NK_ACOS_C1 0.11780662834644318f
+#define NK_ACOS_C2 0.026962917298078537f
+#define NK_ACOS_C3 0.005945307202637196f
+#define NK_ACOS_C4 0.00692177377641201f
+#define NK_ACOS_C5 -0.0036669515538960695f
+#define NK_ACOS_C6 0.0026117281522601843f
+
 #define NK_MAX_STAGES 4
 #define NK_MAX_DEPTH 4
 #define NK_MAX_C 16
@@ -112,6 +122,15 @@ __device__ __forceinline__ float lane_next(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 
+// A zero the compiler cannot see through: added to an LDS index inside a
+// loop it keeps loads of loop-invariant addresses inside the loop (otherwise
+// they are hoisted and pin one register per value for the whole loop).
+__device__ __forceinline__ int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
+
 __device__ __forceinline__ float relu_poly(float u) {
   float p = NK_J1_C5;
   p = __builtin_fmaf(p, u, NK_J1_C4);
@@ -135,6 +154,17 @@ __device__ __forceinline__ float j1_signed(float rho) {
   float u = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(rho), 0.0f, 1.0f);
   float sq = __builtin_amdgcn_sqrtf(u);
   return __builtin_fmaf(u * sq, relu_poly(u), __builtin_fmaxf(rho, 0.0f));
+}
+
+__device__ __forceinline__ float acos_g(float u) {
+  float p = NK_ACOS_C6;
+  p = __builtin_fmaf(p, u, NK_ACOS_C5);
+  p = __builtin_fmaf(p, u, NK_ACOS_C4);
+  p = __builtin_fmaf(p, u, NK_ACOS_C3);
+  p = __builtin_fmaf(p, u, NK_ACOS_C2);
+  p = __builtin_fmaf(p, u, NK_ACOS_C1);
+  p = __builtin_fmaf(p, u, NK_ACOS_C0);
+  return p;
 }
 
 // Logical workgroup index with consecutive indices on the same XCD: the

@@ -31,6 +31,41 @@ struct StageArgs {
   int64_t ldk;
 };
 
+struct StageBwdArgs {
+  int64_t n1, n2;
+  int sym, T;
+  int64_t p0, np;
+  const float* x1;
+  const float* x2;
+  const float2* tab1;
+  const float2* tab2;
+  int tablen, taboff;
+  int C, D;
+  float sb2, seed_scale;
+  const float* in;    // stage input [np][N]^4 (stages after the first)
+  const float* gin;   // adjoint of the next stage's input [np][N/2]^4 (all but the last stage)
+  float* gout;        // adjoint of this stage's input [np][N]^4 (stages after the first)
+  const float* dK;    // cotangent of the block (last stage)
+  int64_t lddk;
+  double* W1;         // per image w sums, table layout [img][tablen]
+  double* W2;
+  double* xbar1;      // per image seed gradients [img][N N C] (first stage)
+  double* xbar2;
+  double* sums;       // [0]: sigma_w2 * dL/dsigma_w2 terms, [1]: dL/dsigma_b2 terms
+};
+
+struct PrepBwdArgs {
+  const float* x;
+  int64_t n;
+  NetDesc net;
+  const double* W;    // w sums of these images [n][tablen]
+  int tablen;
+  double* xbar;       // += image gradients [n][H W C]
+  double* sums;
+  double* scratch;
+  int64_t scratch_per_img;
+};
+
 struct FcArgs {
   const float* x1;
   const float* x2;
@@ -49,6 +84,14 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
 int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream);
+size_t stage_bwd_lds_bytes(int N, int D, bool seed, int C);
+int launch_stage_bwd(int N, const StageBwdArgs& a, bool seed, bool last, bool bias, hipStream_t s);
+int64_t prep_bwd_scratch_doubles(const NetDesc& net);
+int launch_prepare_bwd(const float* x, int64_t n, const NetDesc& net, const double* W, int tablen, double* xbar,
+                       double* sums, double* scratch, int64_t max_blocks, hipStream_t stream);
+int launch_cast_grad(const double* src, float* dst, int64_t n, hipStream_t s);
+int launch_finish_sigma(const double* sums, double sw2, float* dsigma, hipStream_t s);
+int launch_zero_f64(double* p, int64_t n, hipStream_t s);
 int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s);
 int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double* Bd, int64_t c, double* X,
                       hipStream_t s);

@@ -114,3 +114,37 @@ def krr_predict(k_train: torch.Tensor, k_test: torch.Tensor, y: torch.Tensor, ri
                                    pred.data_ptr(), ws.data_ptr(), ws.numel(), _stream(k_train.device))
     _lib.check(rc)
     return pred
+
+
+def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Tensor, depth: Sequence[int],
+                         sigma_w2: float = 2.0, sigma_b2: float = 0.0, need_dx: bool = True,
+                         ws: torch.Tensor | None = None):
+    """Adjoint of myrtle_nngp: returns (dx1, dx2, dsigma[2]) for cotangent dK.
+    For x2=None (symmetric block) dx2 is None and dx1 holds the whole gradient."""
+    _check_images(x1, "x1")
+    sym = x2 is None
+    if sym:
+        x2 = x1
+    else:
+        _check_images(x2, "x2")
+    n1, h, w, c = x1.shape
+    n2 = x2.shape[0]
+    if dK.shape != (n1, n2) or dK.dtype != torch.float32 or not dK.is_cuda:
+        raise ValueError("dK must be a float32 CUDA tensor of shape (n1, n2)")
+    dK = dK.contiguous()
+    cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
+    dx1 = torch.empty_like(x1) if need_dx else None
+    dx2 = None if sym or not need_dx else torch.empty_like(x2)
+    ds = torch.empty(2, dtype=torch.float32, device=x1.device)
+    if ws is None:
+        need = workspace_size(_lib.NK_OP_MYRTLE_BWD, cfg, n1, n2)
+        if need == 0:
+            _lib.check(_lib.lib().nk_myrtle_nngp_backward(None, 0, None, 0, ctypes.byref(cfg), None, 0, None, None,
+                                                          None, None, 0, None))
+        ws = workspace(need, x1.device)
+    rc = _lib.lib().nk_myrtle_nngp_backward(
+        x1.data_ptr(), n1, x2.data_ptr(), n2, ctypes.byref(cfg), dK.data_ptr(), dK.stride(0),
+        None if dx1 is None else dx1.data_ptr(), None if dx2 is None else dx2.data_ptr(), ds.data_ptr(),
+        ws.data_ptr(), ws.numel(), _stream(x1.device))
+    _lib.check(rc)
+    return dx1, dx2, ds
