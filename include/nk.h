@@ -154,15 +154,20 @@ int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t
 /*
  * Cotangents of the held-out squared error of kernel ridge regression,
  *   L = mean((K_ts alpha - Y_t)^2),  alpha = (K_ss + lambda I)^{-1} Y_s,
- * with lambda given explicitly (held fixed):
- *   dK_ts = G alpha^T,  dK_ss = -(A^{-1} K_ts^T G) alpha^T,  G = dL/dpred.
+ * with lambda held fixed (not differentiated):
+ *   dK_ts = G alpha^T,  dK_ss = -(A^{-1} K_ts^T G) alpha^T,  G = dL/dpred,
+ *   A = K_ss + lambda I.
+ * ridge >= 0 with ridge_is_relative == 0 gives lambda = ridge; with
+ * ridge_is_relative != 0, lambda = ridge * mean(diag K_ss).
  * K_ss (n x n), K_ts (m x n), Y_s (n x c), Y_t (m x c) float32 device;
- * dK_ss (n x n), dK_ts (m x n) float32 device outputs; *loss (host double)
- * receives L.  Float64 inside.  Synchronises `stream`.
+ * dK_ss (n x n), dK_ts (m x n) float32 device outputs (dK_ss is the full,
+ * unsymmetrised cotangent); *loss and *lambda_used (host doubles,
+ * lambda_used may be NULL) receive L and lambda.  Float64 inside.
+ * Synchronises `stream`; NK_ENOTPD if A is not positive definite.
  */
 int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t m, const float* Y_s,
-                        const float* Y_t, int64_t c, double lambda, float* dK_ss, float* dK_ts, double* loss,
-                        void* ws, size_t ws_bytes, void* stream);
+                        const float* Y_t, int64_t c, double ridge, int ridge_is_relative, float* dK_ss,
+                        float* dK_ts, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Many Myrtle Gram tiles of uneven size in one scheduled pass: the variance

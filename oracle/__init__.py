@@ -208,3 +208,31 @@ def krr_predict(k_train: np.ndarray, k_test: np.ndarray, y: np.ndarray, ridge_re
     cf = sla.cho_factor(a, lower=True)
     alpha = sla.cho_solve(cf, np.asarray(y, dtype=np.float64))
     return np.asarray(k_test, dtype=np.float64) @ alpha
+
+
+def krr_mse_loss(k_ss, k_ts, y_s, y_t, lam: float) -> float:
+    """Held-out squared error of kernel ridge regression with ridge lam:
+    mean((K_ts (K_ss + lam I)^{-1} Y_s - Y_t)^2), float64 Cholesky solve."""
+    import scipy.linalg as sla
+
+    a = np.asarray(k_ss, dtype=np.float64) + lam * np.eye(len(k_ss))
+    alpha = sla.cho_solve(sla.cho_factor(a, lower=True), np.asarray(y_s, dtype=np.float64))
+    r = np.asarray(k_ts, dtype=np.float64) @ alpha - np.asarray(y_t, dtype=np.float64)
+    return float(np.mean(r * r))
+
+
+def krr_mse_cotangents(k_ss, k_ts, y_s, y_t, lam: float):
+    """d loss / d K_ss and d loss / d K_ts of krr_mse_loss with lam held fixed
+    (reverse mode of the solve: alpha = A^{-1} Y, pred = K_ts alpha)."""
+    import scipy.linalg as sla
+
+    a = np.asarray(k_ss, dtype=np.float64) + lam * np.eye(len(k_ss))
+    cf = sla.cho_factor(a, lower=True)
+    alpha = sla.cho_solve(cf, np.asarray(y_s, dtype=np.float64))
+    kts = np.asarray(k_ts, dtype=np.float64)
+    r = kts @ alpha - np.asarray(y_t, dtype=np.float64)
+    g = 2.0 * r / r.size
+    d_ts = g @ alpha.T
+    z = sla.cho_solve(cf, kts.T @ g)
+    d_ss = -z @ alpha.T
+    return d_ss, d_ts

@@ -77,8 +77,8 @@ def lib():
     L.nk_myrtle_nngp_backward.restype = ci
     L.nk_krr_predict.argtypes = [P, i64, P, i64, P, i64, ctypes.c_double, P, P, sz, P]
     L.nk_krr_predict.restype = ci
-    L.nk_krr_mse_backward.argtypes = [P, i64, P, i64, P, P, i64, ctypes.c_double, P, P,
-                                      ctypes.POINTER(ctypes.c_double), P, sz, P]
+    L.nk_krr_mse_backward.argtypes = [P, i64, P, i64, P, P, i64, ctypes.c_double, ci, P, P,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P, sz, P]
     L.nk_krr_mse_backward.restype = ci
     L.nk_myrtle_nngp_batched.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg), P, sz, P, i32]
     L.nk_myrtle_nngp_batched.restype = ci

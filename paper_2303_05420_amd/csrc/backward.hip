@@ -50,6 +50,19 @@ __host__ __device__ inline size_t bwd_slot_lds_bytes(int D, bool seed, int C) {
   return (t + 15) & ~(size_t)15;
 }
 
+// Sum of v over the segments of this wave that belong to the same pair: the
+// segments share their first-image pixel (row, lane) mapping, so their
+// contributions to that pixel can be combined before one LDS atomic (atomic
+// adds that hit one address from several lanes of an instruction serialise).
+template <int N>
+__device__ __forceinline__ float seg_sum(float v) {
+  constexpr int TPP = BCfg<N>::TPP;
+  constexpr int span = TPP < 64 ? TPP : 64;  // lanes of one pair inside a wave
+#pragma unroll
+  for (int off = N; off < span; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // reverse of one [3x3 conv, ReLU] layer; Aw holds the layer input, G the
 // adjoint of the layer output on entry and of the layer input on return
 // forward layer with the first-ReLU (signed) handling chosen at run time
@@ -84,7 +97,7 @@ template <int N, bool BIAS>
 __device__ __forceinline__ void tile_layer_bwd(const float (&Aw)[N], float (&G)[N], const float2* __restrict__ c1,
                                                const float2* __restrict__ c2, int seam, float mL, float mR,
                                                float sb2, float* __restrict__ w1, float* __restrict__ w2, int ix,
-                                               int jx, int ky, float& sw, float& sb, bool sgn) {
+                                               int jx, int ky, float& sw, float& sb, bool sgn, bool lead) {
   float hm = 0.f;
   float h0 = hsum3(Aw[0], mL, mR);
 #pragma unroll
@@ -114,7 +127,8 @@ __device__ __forceinline__ void tile_layer_bwd(const float (&Aw)[N], float (&G)[
     const float rhob = gb * ss * Jp;
     const float vb = rhob * rr;
     const float w = gb * out - rhob * rho;
-    atomicAdd(&w1[r * N + ix], w);
+    const float wsum = seg_sum<N>(w);
+    if (lead) atomicAdd(&w1[r * N + ix], wsum);
     atomicAdd(&w2[((r + ky) & (N - 1)) * N + jx], w);
     sw = __builtin_fmaf(gb, out, sw);
     sb += vb;
@@ -223,6 +237,9 @@ __global__ __launch_bounds__(BCfg<N>::THREADS) void stage_bwd_kernel(const Stage
     if (args.sym && pa != pb) gpair += args.dK[pb * args.lddk + pa];
   }
 
+  // the lowest segment of this pair inside this wave does the combined
+  // first-image atomics
+  const bool lead = ((tid & 63) % (TPP < 64 ? TPP : 64)) < N;
   double swd = 0.0, sbd = 0.0;
   for (int cc = 0; cc < CPS; ++cc) {
   const int kx = seg + cc * (TPP / N);
@@ -278,7 +295,7 @@ __global__ __launch_bounds__(BCfg<N>::THREADS) void stage_bwd_kernel(const Stage
       const float2* c1 = t1 + l * N * N + ix;
       const float2* c2 = t2 + l * 2 * N * N + ky * N + jx;
       tile_layer_bwd<N, BIAS>(Aw, G, c1, c2, seam, mL, mR, args.sb2, w1 + l * N * N, w2 + l * N * N, ix, jx, ky, sw,
-                              sb, SEED && l == 0);
+                              sb, SEED && l == 0, lead);
       tile_box<N>(G, seam, mL, mR);
     }
     // G = adjoint of the stage input
@@ -296,13 +313,19 @@ __global__ __launch_bounds__(BCfg<N>::THREADS) void stage_bwd_kernel(const Stage
         float* d1 = &xb1[(r * N + ix) * C];
         float* d2 = &xb2[(jy * N + jx) * C];
         const int c1 = C > 1 ? 1 : 0, c2 = C > 2 ? 2 : 0, c3 = C > 3 ? 3 : 0;
-        atomicAdd(d1, gb * w.x);
+        const float s0 = seg_sum<N>(gb * w.x);
+        const float s1 = seg_sum<N>(C > 1 ? gb * w.y : 0.f);
+        const float s2 = seg_sum<N>(C > 2 ? gb * w.z : 0.f);
+        const float s3 = seg_sum<N>(C > 3 ? gb * w.w : 0.f);
+        if (lead) {
+          atomicAdd(d1, s0);
+          atomicAdd(d1 + c1, s1);
+          atomicAdd(d1 + c2, s2);
+          atomicAdd(d1 + c3, s3);
+        }
         atomicAdd(d2, gb * u.x);
-        atomicAdd(d1 + c1, C > 1 ? gb * w.y : 0.f);
         atomicAdd(d2 + c1, C > 1 ? gb * u.y : 0.f);
-        atomicAdd(d1 + c2, C > 2 ? gb * w.z : 0.f);
         atomicAdd(d2 + c2, C > 2 ? gb * u.z : 0.f);
-        atomicAdd(d1 + c3, C > 3 ? gb * w.w : 0.f);
         atomicAdd(d2 + c3, C > 3 ? gb * u.w : 0.f);
         if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }

@@ -176,6 +176,76 @@ __global__ __launch_bounds__(256) void krr_matmul_kernel(const float* __restrict
   out[e] = (float)s;
 }
 
+// pred = K_ts alpha (m x c); resid = pred - Y_t; G = 2 resid / (m c); sq = resid^2
+__global__ __launch_bounds__(256) void krr_resid_kernel(const float* __restrict__ Kts, int64_t m, int64_t n,
+                                                        const double* __restrict__ alpha, int64_t c,
+                                                        const float* __restrict__ Yt, double* __restrict__ G,
+                                                        double* __restrict__ sq) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * c) return;
+  const int64_t i = e / c, k = e - i * c;
+  double p = 0.0;
+  for (int64_t t = 0; t < n; ++t) p += (double)Kts[i * n + t] * alpha[t * c + k];
+  const double r = p - (double)Yt[e];
+  G[e] = 2.0 * r / (double)(m * c);
+  sq[e] = r * r;
+}
+
+// loss = sum(sq) / count, fixed-order reduction in one workgroup
+__global__ __launch_bounds__(256) void krr_loss_kernel(const double* __restrict__ sq, int64_t cnt,
+                                                       double* __restrict__ loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += 256) s += sq[e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = red[0] / (double)cnt;
+}
+
+// B (n x c) = K_ts^T G
+__global__ __launch_bounds__(256) void krr_ktg_kernel(const float* __restrict__ Kts, int64_t m, int64_t n,
+                                                      const double* __restrict__ G, int64_t c,
+                                                      double* __restrict__ B) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t t = e / c, k = e - t * c;
+  double s = 0.0;
+  for (int64_t i = 0; i < m; ++i) s += (double)Kts[i * n + t] * G[i * c + k];
+  B[e] = s;
+}
+
+// out (rows x cols, float) = scale * U V^T with U (rows x c), V (cols x c) double
+__global__ __launch_bounds__(256) void krr_outer_kernel(const double* __restrict__ U, int64_t rows,
+                                                        const double* __restrict__ V, int64_t cols, int64_t c,
+                                                        double scale, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, t = e - i * cols;
+  double s = 0.0;
+  for (int64_t k = 0; k < c; ++k) s += U[i * c + k] * V[t * c + k];
+  out[e] = (float)(scale * s);
+}
+
+int launch_krr_mse_bwd(const float* Kts, int64_t m, int64_t n, const double* alpha, int64_t c, const float* Yt,
+                       double* G, double* sq, double* loss, double* B, hipStream_t s) {
+  const unsigned g1 = (unsigned)((m * c + 255) / 256), g2 = (unsigned)((n * c + 255) / 256);
+  hipLaunchKernelGGL(krr_resid_kernel, dim3(g1), dim3(256), 0, s, Kts, m, n, alpha, c, Yt, G, sq);
+  hipLaunchKernelGGL(krr_loss_kernel, dim3(1), dim3(256), 0, s, sq, m * c, loss);
+  hipLaunchKernelGGL(krr_ktg_kernel, dim3(g2), dim3(256), 0, s, Kts, m, n, G, c, B);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_krr_outer(const double* U, int64_t rows, const double* V, int64_t cols, int64_t c, double scale,
+                     float* out, hipStream_t s) {
+  hipLaunchKernelGGL(krr_outer_kernel, dim3((unsigned)((rows * cols + 255) / 256)), dim3(256), 0, s, U, rows, V, cols,
+                     c, scale, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s) {
   for (int64_t k = 0; k < n; k += CH_NB) {
     const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);

@@ -201,6 +201,28 @@ int64_t max_chunk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size_t w
   return std::min(c, npairs);
 }
 
+struct KrrPlan {
+  size_t A = 0, mean = 0, info = 0, X = 0, B = 0, Z = 0, G = 0, sq = 0, loss = 0, total = 0;
+};
+
+// n: train size; w = max(m test, c targets)
+KrrPlan krr_plan(int64_t n, int64_t w) {
+  KrrPlan p;
+  Bump b;
+  w = std::max<int64_t>(w, 1);
+  p.A = b.take(sizeof(double) * (size_t)n * n);
+  p.mean = b.take(sizeof(double) * 2);
+  p.info = b.take(sizeof(int) * 4);
+  p.X = b.take(sizeof(double) * (size_t)n * w);
+  p.B = b.take(sizeof(double) * (size_t)n * w);
+  p.Z = b.take(sizeof(double) * (size_t)n * w);
+  p.G = b.take(sizeof(double) * (size_t)w * w);
+  p.sq = b.take(sizeof(double) * (size_t)w * w);
+  p.loss = b.take(sizeof(double) * 2);
+  p.total = b.off + 256;
+  return p;
+}
+
 template <class T>
 T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
@@ -320,16 +342,8 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
       const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
       return plan_bwd(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 512 * NK_MAX_STAGES;
     }
-    case NK_OP_KRR: {
-      Bump b;
-      b.take(sizeof(double) * (size_t)n1 * n1);
-      b.take(sizeof(double) * 2);
-      b.take(sizeof(int) * 4);
-      b.take(sizeof(double) * (size_t)n1 * std::max<int64_t>(n2, 1));
-      b.take(sizeof(double) * (size_t)n1 * std::max<int64_t>(n2, 1));
-      b.take(sizeof(double) * (size_t)std::max<int64_t>(n2, 1) * std::max<int64_t>(n2, 1));
-      return b.off + 256;
-    }
+    case NK_OP_KRR:
+      return krr_plan(n1, n2).total;
     default:
       return 0;
   }
@@ -501,11 +515,11 @@ int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t
   if (n > 16384) return fail(NK_EUNSUPPORTED, "n > 16384");
   const size_t need = nk_workspace_size(NK_OP_KRR, nullptr, n, std::max(m, c));
   if (!ws || ws_bytes < need) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", need);
-  Bump b;
-  double* A = at<double>(ws, b.take(sizeof(double) * n * n));
-  double* mean = at<double>(ws, b.take(sizeof(double) * 2));
-  int* info = at<int>(ws, b.take(sizeof(int) * 4));
-  double* X = at<double>(ws, b.take(sizeof(double) * n * c));
+  const KrrPlan kp = krr_plan(n, std::max(m, c));
+  double* A = at<double>(ws, kp.A);
+  double* mean = at<double>(ws, kp.mean);
+  int* info = at<int>(ws, kp.info);
+  double* X = at<double>(ws, kp.X);
   hipStream_t s = (hipStream_t)stream;
   if (nk::launch_krr_build(K_train, n, ridge_rel, 0.0, mean, A, info, s)) return hip_fail("krr build");
   if (nk::launch_cholesky(A, n, info, s)) return hip_fail("cholesky");
@@ -519,11 +533,43 @@ int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t
 }
 
 int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t m, const float* Y_s,
-                        const float* Y_t, int64_t c, double lambda, float* dK_ss, float* dK_ts, double* loss,
-                        void* ws, size_t ws_bytes, void* stream) {
-  (void)K_ss; (void)n; (void)K_ts; (void)m; (void)Y_s; (void)Y_t; (void)c; (void)lambda; (void)dK_ss;
-  (void)dK_ts; (void)loss; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(NK_EUNSUPPORTED, "nk_krr_mse_backward is not available in this build");
+                        const float* Y_t, int64_t c, double ridge, int ridge_is_relative, float* dK_ss,
+                        float* dK_ts, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream) {
+  if (!K_ss || !K_ts || !Y_s || !Y_t || !dK_ss || !dK_ts || !loss) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || m <= 0 || c <= 0) return fail(NK_EINVAL, "need n, m, c > 0");
+  if (!(ridge >= 0.0)) return fail(NK_EINVAL, "ridge must be >= 0");
+  if (n > 16384) return fail(NK_EUNSUPPORTED, "n > 16384");
+  const KrrPlan kp = krr_plan(n, std::max(m, c));
+  if (!ws || ws_bytes < kp.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", kp.total);
+  double* A = at<double>(ws, kp.A);
+  double* mean = at<double>(ws, kp.mean);
+  int* info = at<int>(ws, kp.info);
+  double* X = at<double>(ws, kp.X);
+  double* B = at<double>(ws, kp.B);
+  double* Z = at<double>(ws, kp.Z);
+  double* G = at<double>(ws, kp.G);
+  double* sq = at<double>(ws, kp.sq);
+  double* dloss = at<double>(ws, kp.loss);
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("krr_mse_backward", s);
+  if (nk::launch_krr_build(K_ss, n, ridge_is_relative ? ridge : -1.0, ridge, mean, A, info, s))
+    return hip_fail("krr build");
+  if (nk::launch_cholesky(A, n, info, s)) return hip_fail("cholesky");
+  if (nk::launch_chol_solve(A, n, Y_s, nullptr, c, X, s)) return hip_fail("cholesky solve");
+  if (nk::launch_krr_mse_bwd(K_ts, m, n, X, c, Y_t, G, sq, dloss, B, s)) return hip_fail("krr cotangent");
+  if (nk::launch_chol_solve(A, n, nullptr, B, c, Z, s)) return hip_fail("cholesky solve");
+  if (nk::launch_krr_outer(G, m, X, n, c, 1.0, dK_ts, s)) return hip_fail("krr outer");
+  if (nk::launch_krr_outer(Z, n, X, n, c, -1.0, dK_ss, s)) return hip_fail("krr outer");
+  int h_info = 0;
+  if (hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return hip_fail("krr");
+  double h_mean = 0.0;
+  if (hipMemcpyAsync(loss, dloss, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return hip_fail("krr");
+  if (ridge_is_relative && hipMemcpyAsync(&h_mean, mean, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return hip_fail("krr");
+  if (hipStreamSynchronize(s) != hipSuccess) return hip_fail("krr sync");
+  if (lambda_used) *lambda_used = ridge_is_relative ? ridge * h_mean : ridge;
+  if (h_info) return fail(NK_ENOTPD, "K_ss + lambda I is not positive definite");
+  return ok();
 }
 
 int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg, void* ws,

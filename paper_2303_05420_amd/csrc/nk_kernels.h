@@ -97,6 +97,10 @@ int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double*
                       hipStream_t s);
 int launch_krr_build(const float* K, int64_t n, double ridge_rel, double lam_abs, double* mean, double* A,
                      int* info, hipStream_t s);
+int launch_krr_mse_bwd(const float* Kts, int64_t m, int64_t n, const double* alpha, int64_t c, const float* Yt,
+                       double* G, double* sq, double* loss, double* B, hipStream_t s);
+int launch_krr_outer(const double* U, int64_t rows, const double* V, int64_t cols, int64_t c, double scale,
+                     float* out, hipStream_t s);
 int launch_krr_matmul(const float* K, int64_t m, int64_t n, int64_t ld, const double* X, int64_t c, float* out,
                       hipStream_t s);
 

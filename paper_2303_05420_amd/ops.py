@@ -148,3 +148,29 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
         ws.data_ptr(), ws.numel(), _stream(x1.device))
     _lib.check(rc)
     return dx1, dx2, ds
+
+
+def krr_mse_backward(k_ss: torch.Tensor, k_ts: torch.Tensor, y_s: torch.Tensor, y_t: torch.Tensor, ridge: float,
+                     relative: bool = False):
+    """Cotangents of L = mean((K_ts (K_ss + lam I)^{-1} Y_s - Y_t)^2) with lam
+    held fixed (lam = ridge, or ridge * mean diag K_ss if relative):
+    returns (dK_ss, dK_ts, L, lam)."""
+    for t, nm in ((k_ss, "k_ss"), (k_ts, "k_ts"), (y_s, "y_s"), (y_t, "y_t")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous float32 CUDA tensor")
+    n = k_ss.shape[0]
+    m = k_ts.shape[0]
+    c = y_s.shape[1]
+    if k_ss.shape != (n, n) or k_ts.shape != (m, n) or y_s.shape != (n, c) or y_t.shape != (m, c):
+        raise ValueError("shape mismatch")
+    dss = torch.empty_like(k_ss)
+    dts = torch.empty_like(k_ts)
+    loss = ctypes.c_double(0.0)
+    lam = ctypes.c_double(0.0)
+    ws = workspace(workspace_size(_lib.NK_OP_KRR, None, n, max(m, c)), k_ss.device)
+    rc = _lib.lib().nk_krr_mse_backward(k_ss.data_ptr(), n, k_ts.data_ptr(), m, y_s.data_ptr(), y_t.data_ptr(), c,
+                                        float(ridge), 1 if relative else 0, dss.data_ptr(), dts.data_ptr(),
+                                        ctypes.byref(loss), ctypes.byref(lam), ws.data_ptr(), ws.numel(),
+                                        _stream(k_ss.device))
+    _lib.check(rc)
+    return dss, dts, float(loss.value), float(lam.value)

@@ -243,3 +243,29 @@ def test_krr_interpolates_training_set_at_tiny_ridge():
     y = rng.standard_normal((20, 2))
     got = oracle.krr_predict(K, K, y, 1e-12)
     assert np.max(np.abs(got - y)) < 1e-9
+
+
+def test_krr_mse_cotangents_match_finite_differences():
+    rng = np.random.default_rng(12)
+    n, m, c = 9, 6, 3
+    a = rng.standard_normal((n, n + 3))
+    kss = a @ a.T / (n + 3)
+    kts = rng.standard_normal((m, n))
+    ys = rng.standard_normal((n, c))
+    yt = rng.standard_normal((m, c))
+    lam = 0.05
+    dss, dts = oracle.krr_mse_cotangents(kss, kts, ys, yt, lam)
+    h = 1e-6
+    # K_ss is symmetric: perturb (i, j) and (j, i) together; the directional
+    # derivative is dss[i, j] + dss[j, i] (dss[i, i] on the diagonal)
+    for (i, j) in [(0, 0), (2, 5), (8, 1)]:
+        e = np.zeros_like(kss)
+        e[i, j] = e[j, i] = 1.0
+        fd = (oracle.krr_mse_loss(kss + h * e, kts, ys, yt, lam) - oracle.krr_mse_loss(kss - h * e, kts, ys, yt, lam)) / (2 * h)
+        ref = dss[i, j] + (dss[j, i] if i != j else 0.0)
+        assert abs(fd - ref) <= 1e-7 * max(1.0, abs(dss).max())
+    for (i, j) in [(0, 0), (5, 8), (3, 4)]:
+        kp = kts.copy(); kp[i, j] += h
+        km = kts.copy(); km[i, j] -= h
+        fd = (oracle.krr_mse_loss(kss, kp, ys, yt, lam) - oracle.krr_mse_loss(kss, km, ys, yt, lam)) / (2 * h)
+        assert abs(fd - dts[i, j]) <= 1e-7 * max(1.0, abs(dts).max())
