@@ -424,7 +424,7 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
   const bool sym = (x1 == x2) && (n1 == n2);
   if (sym && dx2 && dx2 != dx1) return fail(NK_EINVAL, "symmetric block: dx2 must be NULL or equal to dx1");
   for (int s = 0; s < net.S; ++s)
-    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0, net.C) > 160 * 1024)
+    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0) > 160 * 1024)
       return fail(NK_EUNSUPPORTED, "adjoint of stage %d needs more than 160 KiB of LDS", s);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   const int64_t chunk = max_chunk_bwd(net, n1, n2, sym, ws_bytes, npairs);
@@ -485,12 +485,12 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
       b.in = st > 0 ? bufs[st] : nullptr;
       b.gin = st + 1 < net.S ? gbufs[st + 1] : nullptr;
       b.gout = st > 0 ? gbufs[st] : nullptr;
-      b.dK = dK; b.lddk = lddk;
+      b.dK = dK; b.lddk = lddk; b.last = st + 1 == net.S ? 1 : 0;
       b.W1 = W1; b.W2 = W2; b.xbar1 = xb1; b.xbar2 = xb2; b.sums = sums;
       char nm[48];
       snprintf(nm, sizeof nm, "myrtle_stage%d_n%d_bwd", st + 1, net.hw >> st);
       ProfScope ps(nm, s);
-      if (nk::launch_stage_bwd(net.hw >> st, b, st == 0, st + 1 == net.S, net.sb2 != 0.f, s))
+      if (nk::launch_stage_bwd(net.hw >> st, b, st == 0, s))
         return hip_fail("adjoint stage kernel");
     }
   }

@@ -47,6 +47,7 @@ struct StageBwdArgs {
   float* gout;        // adjoint of this stage's input [np][N]^4 (stages after the first)
   const float* dK;    // cotangent of the block (last stage)
   int64_t lddk;
+  int last;           // 1 for the last stage (adjoint from dK), else from gin
   double* W1;         // per image w sums, table layout [img][tablen]
   double* W2;
   double* xbar1;      // per image seed gradients [img][N N C] (first stage)
@@ -84,8 +85,11 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
 int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream);
-size_t stage_bwd_lds_bytes(int N, int D, bool seed, int C);
-int launch_stage_bwd(int N, const StageBwdArgs& a, bool seed, bool last, bool bias, hipStream_t s);
+size_t stage_bwd_lds_bytes(int N, int D, bool seed);
+int launch_stage_bwd(int N, const StageBwdArgs& a, bool seed, hipStream_t s);
+int launch_stage_bwd_32(const StageBwdArgs& a, bool seed, hipStream_t s);
+int launch_stage_bwd_16(const StageBwdArgs& a, bool seed, hipStream_t s);
+int launch_stage_bwd_small(int N, const StageBwdArgs& a, bool seed, hipStream_t s);
 int64_t prep_bwd_scratch_doubles(const NetDesc& net);
 int launch_prepare_bwd(const float* x, int64_t n, const NetDesc& net, const double* W, int tablen, double* xbar,
                        double* sums, double* scratch, int64_t max_blocks, hipStream_t stream);
