@@ -5,7 +5,11 @@ MI355X through libnk.
 
 A step is one nk_myrtle_nngp call on the whole block (variance tables, the
 three fused stage kernels, readout and block write) with the images already
-in device memory.  Prints one JSON line; see the design doc for the fields.
+in device memory.  Beside it the run times one forward + backward pass of the
+differentiable workload (Myrtle-5 at 32x32x3: kernel ridge regression of 256
+learnable support images onto 2048 target images, gradients with respect to
+the support pixels and both sigmas) and reports it as fwd+bwd pairs/s.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Myrtle-10 NNGP kernel entries/s at 32x32x3; fwd+bwd pairs/s; %FP32 VALU peak"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA, 64 lanes)
-PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_pmc.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_hbm_counters.md")
 STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage.hip")
 
 
@@ -33,9 +37,10 @@ def _args():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=4096, help="block side (the headline workload is 4096)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=32, help="side of the oracle sample sub-block")
+    p.add_argument("--cpu-sample", type=int, default=48, help="side of the oracle sample sub-block")
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run a plain device copy of this many MiB (counter calibration runs)")
+    p.add_argument("--no-fwd-bwd", action="store_true", help="skip the fwd+bwd measurement")
     return p.parse_args()
 
 
@@ -47,8 +52,9 @@ def _traffic(stage_launch_pairs: int):
     """HBM bytes per stage-1 launch from the committed counter summary, or None
     when there is none or the kernel source changed since it was taken."""
     try:
-        d = json.load(open(PMC_FILE))
-    except (OSError, ValueError):
+        text = open(PMC_FILE).read()
+        d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
         return None
     if d.get("stage_src_sha256_16") != _src_hash(STAGE_SRC):
         return None
@@ -56,6 +62,47 @@ def _traffic(stage_launch_pairs: int):
     if per_pair is None:
         return None
     return float(per_pair) * stage_launch_pairs
+
+
+def _fwd_bwd(torch):
+    """One timed forward + backward pass of the kernel-ridge-regression loss
+    through the Myrtle-5 NNGP (after one untimed pass)."""
+    import synth
+    from paper_2303_05420_amd import _lib, krr_grad
+
+    w = synth.WORKLOADS["myrtle5_krr_grad"]
+    ns, nt = w["n_support"], w["n_target"]
+    xs = torch.from_numpy(synth.correlated_images(ns, 32, 32, 3, w["length"], w["seeds"][0])).cuda()
+    xt = torch.from_numpy(synth.correlated_images(nt, 32, 32, 3, w["length"], w["seeds"][1])).cuda()
+    ys = torch.from_numpy(synth.balanced_labels(ns, 10)).cuda()
+    yt = torch.from_numpy(synth.teacher_labels(synth.correlated_images(nt, 32, 32, 3, w["length"], w["seeds"][1]),
+                                               10, w["seeds"][2])).cuda()
+
+    def run():
+        return krr_grad.krr_mse_loss_and_grad(xs, ys, xt, yt, w["depth"], w["sigma_w2"], w["sigma_b2"],
+                                              w["ridge_rel"])
+
+    run()
+    torch.cuda.synchronize()
+    print("fwd+bwd warm-up done", file=sys.stderr, flush=True)
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    loss, dxs, ds, lam = run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    pairs = ns * (ns + 1) // 2 + nt * ns
+    fwd_ms = sum(v[1] for k, v in prof.items() if k.startswith("myrtle_stage") and not k.endswith("_bwd"))
+    bwd_ms = sum(v[1] for k, v in prof.items() if k.endswith("_bwd"))
+    print(f"fwd+bwd: {dt * 1e3:.1f} ms for {pairs} pairs", file=sys.stderr, flush=True)
+    return {"value": round(pairs / dt, 3), "unit": "pairs/s", "pairs": pairs, "ms": round(dt * 1e3, 3),
+            "workload": f"Myrtle-5 NNGP at 32x32x3, KRR of {ns} learnable support images onto {nt} targets "
+                        f"(K_ss symmetric + K_ts), loss + d/d(support pixels) + d/d(sigma_w2, sigma_b2)",
+            "loss": loss, "dsigma": [float(v) for v in ds.cpu().tolist()],
+            "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
+            "stage_kernels_fwd_ms": round(fwd_ms, 3), "stage_kernels_bwd_ms": round(bwd_ms, 3)}
 
 
 def main():
@@ -141,6 +188,8 @@ def main():
     flops_pair = workmodel.flops_per_pair(hw, 3, depth)
     whole = flops_pair * pairs / (ms_step / 1e3) / 1e12
 
+    fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
+
     cpu = None
     parity = None
     if not a.no_cpu_baseline:
@@ -185,6 +234,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "fwd_bwd": fwd_bwd,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))

@@ -65,9 +65,9 @@ enum { NK_OP_FC = 0, NK_OP_MYRTLE = 1, NK_OP_MYRTLE_BWD = 2, NK_OP_KRR = 3, NK_O
  * sigma_w2 / C_in and bias sigma_b2.  Myrtle-5 = {2,1,1}, Myrtle-7 =
  * {2,2,2}, Myrtle-10 = {3,3,3}.
  *
- * Supported: H == W, H >> (n_stages-1) in {2,4,8,16,32} at every stage
- * (H in 2..64 a power of two with all stage sizes <= 64), filter == 3,
- * 1 <= n_stages <= 4, 0 <= depth[s] <= 4 with depth[0] >= 1, 1 <= C <= 16,
+ * Supported: H == W a power of two with 2 <= H <= 32 and every stage at
+ * least 2 x 2 (H >> (n_stages-1) >= 2), filter == 3, 1 <= n_stages <= 4,
+ * 0 <= depth[s] <= 4 with depth[0] >= 1, 1 <= C <= 4,
  * sigma_w2 > 0, sigma_b2 >= 0.  Anything else returns NK_EUNSUPPORTED
  * (or NK_EINVAL for values that define no network).
  */
