@@ -100,8 +100,9 @@ typedef struct {
  * Workspace bytes needed by an operation.  cfg points at the op's config
  * struct (nk_fc_cfg for NK_OP_FC, nk_myrtle_cfg for the Myrtle ops, NULL for
  * NK_OP_KRR).  n1/n2: block sizes (KRR: n1 = n train, n2 = max(m test, c
- * targets)); for NK_OP_MYRTLE_BATCHED n1 = total distinct images, n2 = total
- * pairs.  Returns 0 for invalid arguments.
+ * targets)); for NK_OP_MYRTLE_BATCHED n1 = image rows to prepare (summed
+ * over distinct image arrays), n2 = number of tiles, sized for chunks of
+ * 16384 pairs.  Returns 0 for invalid arguments.
  */
 size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2);
 
@@ -170,16 +171,55 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
                         float* dK_ts, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Many Myrtle Gram tiles of uneven size in one scheduled pass: the variance
- * tables of every distinct image are prepared once and the pairs of all
- * tiles are dealt over one grid in cost order.  Tiles may share image
- * arrays (the same x pointer) and must not overlap in their K outputs.
- * If `graph` is non-zero the pass is captured into a hipGraph on first use
- * and replayed while the tile list, pointers and workspace are unchanged.
- * Same accuracy and determinism as nk_myrtle_nngp.
+ * Many Myrtle Gram tiles of uneven size in one scheduled pass (the paper
+ * computes a large kernel as many independent blocks, Sec. "Approaches to
+ * large-scale kernel methods").  The variance tables of every distinct
+ * image array are prepared once (tiles that pass the same x pointer share
+ * them; the rows used are the largest n of the tiles naming that pointer),
+ * and the pairs of all tiles form one work list that runs in full chunks
+ * through the stage kernels, so no tile pays its own launch tail.  A tile
+ * with x1 == x2 and n1 == n2 is symmetric (upper triangle computed and
+ * mirrored).  Tiles must not overlap in their K outputs.  K values are
+ * bitwise identical to nk_myrtle_nngp on the same tile.
+ *
+ * Schedule.  On the first call for a network configuration the library
+ * times the first stage kernel on the pass's own first pairs under each
+ * candidate schedule -- pairs per stage pass (8192, 16384, 32768, as far as
+ * the workspace allows), side of the image tile that orders pairs (8, 16,
+ * 32), and a persistent grid (all workgroups resident, the workgroups of
+ * each XCD walking one contiguous range of the work list) or one workgroup
+ * per work unit -- and keeps the fastest for the process
+ * (nk_myrtle_batched_tuning reports the timings).  That call synchronises
+ * `stream`; later calls do not.
+ *
+ * If `graph` is non-zero the pass (table preparation and all stage
+ * launches) is captured into a hipGraph the first time this exact pass is
+ * seen (same tiles, configuration, workspace pointer and size) and replayed
+ * on `stream` afterwards; the tile table is uploaded into the workspace on
+ * every call before the launch.  Graphs are cached per process (the 8 most
+ * recent).  ws: at least nk_myrtle_nngp_batched_workspace(...) bytes.
  */
 int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg, void* ws,
                            size_t ws_bytes, void* stream, int32_t graph);
+
+/* Workspace bytes for nk_myrtle_nngp_batched on this tile list (0 if the
+ * arguments are invalid). */
+size_t nk_myrtle_nngp_batched_workspace(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg);
+
+/* One timed schedule candidate of the batched pass. */
+typedef struct {
+  int64_t chunk;      /* pairs per stage pass */
+  int32_t pair_tile;  /* image-tile side of the pair order */
+  int32_t persistent; /* 1: persistent XCD-ordered grid, 0: one workgroup per unit */
+  double us_per_pair; /* measured first-stage time per pair */
+} nk_batched_candidate;
+
+/* Timings of the candidates tried for this network (up to max_entries into
+ * out, may be NULL) and the chosen one (into *chosen, may be NULL).  Returns
+ * the number of candidates, or NK_EINVAL if no batched pass has been tuned
+ * for this configuration in this process. */
+int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
+                             nk_batched_candidate* chosen);
 
 /*
  * Kernel timing (tracing).  After nk_profile_enable(1), every launch of the

@@ -41,6 +41,11 @@ class Tile(ctypes.Structure):
                 ("K", ctypes.c_void_p), ("ldk", ctypes.c_int64)]
 
 
+class BatchedCandidate(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int64), ("pair_tile", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("us_per_pair", ctypes.c_double)]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -82,6 +87,11 @@ def lib():
     L.nk_krr_mse_backward.restype = ci
     L.nk_myrtle_nngp_batched.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg), P, sz, P, i32]
     L.nk_myrtle_nngp_batched.restype = ci
+    L.nk_myrtle_nngp_batched_workspace.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg)]
+    L.nk_myrtle_nngp_batched_workspace.restype = sz
+    L.nk_myrtle_batched_tuning.argtypes = [ctypes.POINTER(MyrtleCfg), ctypes.POINTER(BatchedCandidate), ci,
+                                           ctypes.POINTER(BatchedCandidate)]
+    L.nk_myrtle_batched_tuning.restype = ci
     L.nk_profile_enable.argtypes = [ci]
     L.nk_profile_enable.restype = ci
     L.nk_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ci, ci]

@@ -48,6 +48,7 @@ std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
 std::map<std::string, std::pair<int64_t, double>> g_prof_done;
+thread_local bool g_capturing = false;  // no per-launch events inside a graph capture
 
 // Brackets one launch with events when profiling is on.
 struct ProfScope {
@@ -57,7 +58,7 @@ struct ProfScope {
   ProfScope(const char* name, hipStream_t stream) : s(stream) {
     {
       std::lock_guard<std::mutex> g(g_prof_mu);
-      on = g_prof_on;
+      on = g_prof_on && !g_capturing;
     }
     if (!on) return;
     rec.name = name;
@@ -228,6 +229,238 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+
+// ---- batched tiles (many uneven Gram tiles in one scheduled pass) --------
+
+// Schedule parameters of a batched pass: pairs per stage pass, image-tile
+// side of the pair order, persistent grid or one workgroup per unit.
+struct BatchParams {
+  int64_t chunk = kDefaultChunk;
+  int T = kPairTile;
+  int persist = 0;
+};
+
+struct TuneRecord {
+  BatchParams best;
+  std::vector<nk_batched_candidate> cands;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneRecord> g_tune;  // per network (one process-wide choice)
+
+std::string net_key(const NetDesc& net) {
+  char b[160];
+  snprintf(b, sizeof b, "hw%d C%d S%d d%d,%d,%d,%d b%d", net.hw, net.C, net.S, net.depth[0], net.depth[1],
+           net.depth[2], net.depth[3], net.sb2 != 0.f ? 1 : 0);
+  return b;
+}
+
+struct BatchLayout {
+  std::vector<nk::TileDesc> desc;   // host copy of the tile table
+  std::vector<std::pair<const float*, int64_t>> images;  // distinct image arrays and the rows used
+  int64_t rows = 0;                 // table rows (images prepared)
+  int64_t npairs = 0;
+};
+
+int batch_layout(const nk_tile* tiles, int32_t ntiles, const NetDesc& net, BatchLayout* L) {
+  std::map<const float*, size_t> idx;
+  for (int32_t t = 0; t < ntiles; ++t) {
+    const nk_tile& u = tiles[t];
+    if (!u.x1 || !u.x2 || !u.K) return fail(NK_EINVAL, "tile %d: null pointer", t);
+    if (u.n1 <= 0 || u.n2 <= 0) return fail(NK_EINVAL, "tile %d: n1 and n2 must be positive", t);
+    if (u.ldk < u.n2) return fail(NK_EINVAL, "tile %d: ldk < n2", t);
+    const float* xs[2] = {u.x1, u.x2};
+    const int64_t ns[2] = {u.n1, u.n2};
+    for (int k = 0; k < 2; ++k) {
+      auto it = idx.find(xs[k]);
+      if (it == idx.end()) {
+        idx[xs[k]] = L->images.size();
+        L->images.push_back({xs[k], ns[k]});
+      } else {
+        L->images[it->second].second = std::max(L->images[it->second].second, ns[k]);
+      }
+    }
+  }
+  std::vector<int64_t> row0(L->images.size());
+  for (size_t i = 0; i < L->images.size(); ++i) {
+    row0[i] = L->rows;
+    L->rows += L->images[i].second;
+  }
+  int64_t p = 0;
+  for (int32_t t = 0; t < ntiles; ++t) {
+    const nk_tile& u = tiles[t];
+    nk::TileDesc d;
+    memset(&d, 0, sizeof d);
+    d.sym = (u.x1 == u.x2 && u.n1 == u.n2) ? 1 : 0;
+    d.p_begin = p;
+    d.n1 = u.n1;
+    d.n2 = u.n2;
+    d.t1 = row0[idx[u.x1]];
+    d.t2 = row0[idx[u.x2]];
+    d.x1 = u.x1;
+    d.x2 = u.x2;
+    d.K = u.K;
+    d.ldk = u.ldk;
+    p += nk::pair_count(u.n1, u.n2, d.sym);
+    L->desc.push_back(d);
+  }
+  L->npairs = p;
+  (void)net;
+  return NK_OK;
+}
+
+struct BatchPlan {
+  size_t desc = 0, tab = 0, scratch = 0, buf[NK_MAX_STAGES] = {0, 0, 0, 0};
+  size_t total = 0;
+};
+
+BatchPlan plan_batched(const NetDesc& net, int64_t rows, int64_t ntiles, int64_t chunk) {
+  BatchPlan p;
+  Bump b;
+  p.desc = b.take(sizeof(nk::TileDesc) * (size_t)std::max<int64_t>(ntiles, 1));
+  p.tab = b.take((size_t)nk::table_len(net) * sizeof(float2) * rows);
+  const int64_t pb = std::min<int64_t>(std::max<int64_t>(rows, 1), kPrepBlocks);
+  p.scratch = b.take((size_t)nk::prep_scratch_doubles(net) * sizeof(double) * pb);
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    p.buf[s] = b.take(n * n * n * n * sizeof(float) * chunk);
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
+int g_cu_count = 0;
+
+int cu_count() {
+  if (g_cu_count <= 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      return 0;
+    g_cu_count = n;
+  }
+  return g_cu_count;
+}
+
+// Stage passes of chunks [p_lo, p_hi) of a batched pass.
+int run_batched_stages(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles, const float2* tab, float* const* bufs,
+                       const BatchParams& bp, int64_t p_lo, int64_t p_hi, int only_stage, hipStream_t stream) {
+  for (int64_t p0 = p_lo; p0 < p_hi; p0 += bp.chunk) {
+    const int64_t np = std::min(bp.chunk, p_hi - p0);
+    for (int s = 0; s < net.S; ++s) {
+      if (only_stage >= 0 && s != only_stage) continue;
+      nk::StageArgs a;
+      memset(&a, 0, sizeof a);
+      a.T = bp.T;
+      a.p0 = p0;
+      a.np = np;
+      a.tiles = ddesc;
+      a.ntiles = ntiles;
+      a.tab1 = tab;
+      a.tab2 = tab;
+      a.tablen = nk::table_len(net);
+      a.taboff = nk::table_off(net, s);
+      a.C = net.C;
+      a.D = net.depth[s];
+      a.sb2 = net.sb2;
+      a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      const bool pool = s + 1 < net.S;
+      a.in = s > 0 ? bufs[s] : nullptr;
+      a.out = pool ? bufs[s + 1] : nullptr;
+      if (bp.persist) {
+        const int occ = nk::stage_occupancy(net.hw >> s, net.depth[s], s == 0, pool, net.sb2 != 0.f);
+        const int cus = cu_count();
+        if (occ <= 0 || cus <= 0) return hip_fail("occupancy query");
+        const int N = net.hw >> s;
+        const int64_t ppwg = N * N >= 256 ? 1 : 256 / (N * N);  // pairs per workgroup of the stage kernel
+        const int64_t units = (np + ppwg - 1) / ppwg;
+        // all workgroups resident (occupancy x CUs), a multiple of the 8 XCDs,
+        // and no more than the units to share
+        int64_t g = (int64_t)occ * cus / 8 * 8;
+        a.persist = (int)std::max<int64_t>(8, std::min<int64_t>(g, (units + 7) / 8 * 8));
+      }
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", s + 1, net.hw >> s);
+      ProfScope ps(nm, stream);
+      if (nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream)) return hip_fail("stage kernel");
+    }
+  }
+  return NK_OK;
+}
+
+// Times the first-stage kernel of the pass under each schedule candidate on
+// the pass's own first pairs and keeps the fastest (results are identical
+// under every candidate: the schedule only permutes pairs).
+int autotune(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles, const float2* tab, float* const* bufs,
+             int64_t npairs, int64_t max_chunk_ws, hipStream_t s, TuneRecord* rec) {
+  // pairs per stage pass: the candidates that fit the workspace, cut to the
+  // pass size (duplicates dropped)
+  std::vector<int64_t> chunks;
+  for (int64_t c : {(int64_t)8192, (int64_t)16384, (int64_t)32768}) {
+    const int64_t e = std::min(std::min(c, max_chunk_ws), npairs);
+    if (e > 0 && std::find(chunks.begin(), chunks.end(), e) == chunks.end()) chunks.push_back(e);
+  }
+  const int Ts[3] = {8, 16, 32};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail("event");
+  double best = 1e30;
+  bool first = true;
+  int rc = NK_OK;
+  for (int64_t c : chunks) {
+    const int64_t np = c;
+    for (int T : Ts) {
+      for (int persist = 0; persist <= 1; ++persist) {
+        BatchParams bp;
+        bp.chunk = c;
+        bp.T = T;
+        bp.persist = persist;
+        if (first) {  // warm-up
+          if ((rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, np, 0, s))) goto done;
+          first = false;
+        }
+        hipEventRecord(e0, s);
+        if ((rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, np, 0, s))) goto done;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = hip_fail("tuning event");
+          goto done;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        nk_batched_candidate cd;
+        cd.chunk = c;
+        cd.pair_tile = T;
+        cd.persistent = persist;
+        cd.us_per_pair = 1e3 * ms / (double)np;
+        rec->cands.push_back(cd);
+        if (cd.us_per_pair < best) {
+          best = cd.us_per_pair;
+          rec->best = bp;
+        }
+      }
+    }
+  }
+done:
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
+}
+
+struct GraphEntry {
+  std::string sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recent last
+hipStream_t g_cap_stream = nullptr;
+
+void drop_graph(GraphEntry& e) {
+  if (e.exec) hipGraphExecDestroy(e.exec);
+  if (e.graph) hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+}
+
 // Myrtle Gram block through the stage kernels (tables already prepared).
 int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym,
                      const float2* tab1, const float2* tab2, float* K, int64_t ldk, float* const* bufs,
@@ -344,6 +577,11 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
     }
     case NK_OP_KRR:
       return krr_plan(n1, n2).total;
+    case NK_OP_MYRTLE_BATCHED: {
+      NetDesc net;
+      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
+      return plan_batched(net, n1, std::max<int64_t>(n2, 1), kDefaultChunk).total + 256 * NK_MAX_STAGES;
+    }
     default:
       return 0;
   }
@@ -574,8 +812,164 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
 
 int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg, void* ws,
                            size_t ws_bytes, void* stream, int32_t graph) {
-  (void)tiles; (void)ntiles; (void)cfg; (void)ws; (void)ws_bytes; (void)stream; (void)graph;
-  return fail(NK_EUNSUPPORTED, "nk_myrtle_nngp_batched is not available in this build");
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!tiles || ntiles <= 0) return fail(NK_EINVAL, "need at least one tile");
+  if (!ws) return fail(NK_EINVAL, "workspace is NULL");
+  BatchLayout L;
+  if ((rc = batch_layout(tiles, ntiles, net, &L))) return rc;
+  const BatchPlan p0 = plan_batched(net, L.rows, ntiles, 0);
+  size_t per = 0;
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    per += n * n * n * n * sizeof(float);
+  }
+  const size_t slack = 256 * NK_MAX_STAGES;
+  if (ws_bytes < p0.total + slack + per)
+    return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)", p0.total + slack + per);
+  const int64_t max_chunk_ws =
+      per == 0 ? (int64_t)1 << 40 : (int64_t)((ws_bytes - p0.total - slack) / per);
+  hipStream_t s = (hipStream_t)stream;
+  const std::string key = net_key(net);
+
+  // tile table -> workspace (every call: the caller may reuse the workspace)
+  BatchPlan pl = plan_batched(net, L.rows, ntiles, std::min<int64_t>(max_chunk_ws, 32768));
+  nk::TileDesc* ddesc = at<nk::TileDesc>(ws, pl.desc);
+  if (nk::launch_put_tiles(L.desc.data(), (int)L.desc.size(), ddesc, s)) return hip_fail("tile table upload");
+  float2* tab = at<float2>(ws, pl.tab);
+  double* scratch = at<double>(ws, pl.scratch);
+  float* bufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  for (int st = 1; st < net.S; ++st) bufs[st] = at<float>(ws, pl.buf[st]);
+
+  auto prepare_all = [&]() -> int {
+    int64_t row = 0;
+    for (auto& im : L.images) {
+      if (nk::launch_prepare(im.first, im.second, net, tab + row * nk::table_len(net), scratch, kPrepBlocks, s))
+        return hip_fail("prepare kernel");
+      row += im.second;
+    }
+    return NK_OK;
+  };
+
+  // schedule: tuned once per network and process
+  BatchParams bp;
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      bp = it->second.best;
+      have = true;
+    }
+  }
+  for (int st = 0; st < net.S; ++st)
+    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f))
+      return hip_fail("stage kernel attributes");
+  if (!have) {
+    {
+      ProfScope ps("myrtle_prepare", s);
+      if ((rc = prepare_all())) return rc;
+    }
+    TuneRecord rec;
+    if ((rc = autotune(net, ddesc, ntiles, tab, bufs, L.npairs, max_chunk_ws, s, &rec))) return rc;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = rec;
+    bp = rec.best;
+  }
+  bp.chunk = std::min(bp.chunk, max_chunk_ws);
+
+  if (!graph) {
+    {
+      ProfScope ps("myrtle_prepare", s);
+      if ((rc = prepare_all())) return rc;
+    }
+    if ((rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, L.npairs, -1, s))) return rc;
+    return ok();
+  }
+
+  // graph: captured on a library stream the first time this exact pass is
+  // seen (tiles, network, workspace, schedule), replayed afterwards
+  char sigb[256];
+  snprintf(sigb, sizeof sigb, "%s|ws%p:%zu|c%lld T%d p%d|", key.c_str(), ws, ws_bytes, (long long)bp.chunk, bp.T,
+           bp.persist);
+  std::string sig(sigb);
+  sig.append(reinterpret_cast<const char*>(L.desc.data()), sizeof(nk::TileDesc) * L.desc.size());
+  for (auto& im : L.images) sig.append(reinterpret_cast<const char*>(&im), sizeof im);
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  GraphEntry* hit = nullptr;
+  for (auto& e : g_graphs)
+    if (e.sig == sig) hit = &e;
+  if (!hit) {
+    if (!g_cap_stream && hipStreamCreateWithFlags(&g_cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return hip_fail("capture stream");
+    GraphEntry e;
+    e.sig = sig;
+    if (hipStreamBeginCapture(g_cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+      return hip_fail("begin capture");
+    g_capturing = true;
+    hipStream_t keep = s;
+    s = g_cap_stream;
+    rc = prepare_all();
+    if (!rc) rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, L.npairs, -1, s);
+    s = keep;
+    g_capturing = false;
+    const hipError_t ec = hipStreamEndCapture(g_cap_stream, &e.graph);
+    if (rc) {
+      if (e.graph) hipGraphDestroy(e.graph);
+      return rc;
+    }
+    if (ec != hipSuccess || !e.graph) return hip_fail("end capture");
+    if (hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(e.graph);
+      return hip_fail("graph instantiate");
+    }
+    if (g_graphs.size() >= 8) {
+      drop_graph(g_graphs.front());
+      g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back(e);
+    hit = &g_graphs.back();
+  }
+  ProfScope ps("myrtle_batched_graph", s);
+  if (hipGraphLaunch(hit->exec, s) != hipSuccess) return hip_fail("graph launch");
+  return ok();
+}
+
+size_t nk_myrtle_nngp_batched_workspace(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg) {
+  NetDesc net;
+  if (!tiles || ntiles <= 0 || check_myrtle(cfg, &net)) return 0;
+  BatchLayout L;
+  if (batch_layout(tiles, ntiles, net, &L)) return 0;
+  return plan_batched(net, L.rows, ntiles, std::min<int64_t>(std::max<int64_t>(L.npairs, 1), 32768)).total +
+         256 * NK_MAX_STAGES;
+}
+
+int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
+                             nk_batched_candidate* chosen) {
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(net_key(net));
+  if (it == g_tune.end()) return fail(NK_EINVAL, "no batched pass has been tuned for this network yet");
+  const TuneRecord& r = it->second;
+  int n = 0;
+  for (auto& c : r.cands) {
+    if (out && n < max_entries) out[n] = c;
+    ++n;
+  }
+  if (chosen) {
+    memset(chosen, 0, sizeof *chosen);
+    chosen->chunk = r.best.chunk;
+    chosen->pair_tile = r.best.T;
+    chosen->persistent = r.best.persist;
+    for (auto& c : r.cands)
+      if (c.chunk == r.best.chunk && c.pair_tile == r.best.T && c.persistent == r.best.persist)
+        chosen->us_per_pair = c.us_per_pair;
+  }
+  ok();
+  return n;
 }
 
 }  // extern "C"

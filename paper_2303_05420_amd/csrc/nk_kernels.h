@@ -14,10 +14,27 @@ struct PrepArgs {
   int64_t scratch_per_img;
 };
 
+// One Gram tile of a batched pass, in device memory.  Its pairs are global
+// pairs [p_begin, p_begin + pair_count(n1, n2, sym)) of the pass; its images'
+// tables are rows t1 + a and t2 + b of the pass's table array.
+struct TileDesc {
+  int64_t p_begin;
+  int64_t n1, n2;
+  int64_t t1, t2;
+  const float* x1;
+  const float* x2;
+  float* K;
+  int64_t ldk;
+  int sym, pad;
+};
+
 struct StageArgs {
   int64_t n1, n2;
   int sym, T;
   int64_t p0, np;  // chunk = pairs [p0, p0 + np) of the block order
+  const TileDesc* tiles;  // batched pass: tile table (NULL: one block given by n1, n2, x1, x2, K)
+  int ntiles;
+  int persist;     // > 0: grid of `persist` workgroups looping over the chunk
   const float* x1;
   const float* x2;
   const float2* tab1;
@@ -84,6 +101,9 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
                    int64_t max_blocks, hipStream_t stream);
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
+int prime_stage(int N, int D, bool seed, bool pool, bool bias);  // kernel attributes, no launch
+int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t stream);
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias);  // resident workgroups per CU
 int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream);
 size_t stage_bwd_lds_bytes(int N, int D, bool seed);
 int launch_stage_bwd(int N, const StageBwdArgs& a, bool seed, hipStream_t s);

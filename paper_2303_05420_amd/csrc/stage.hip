@@ -39,12 +39,72 @@ namespace nk {
 
 
 
+// Pair p of the pass -> table rows of both images, their pixels (first
+// stage) and where its kernel value goes (and its mirror in a symmetric
+// block).  One block: the block order of pair_of.  Batched pass: the tile
+// holding p (binary search over the tiles' first pairs), then its block order.
+__device__ inline void resolve_pair(const StageArgs& a, int64_t p, int64_t img_floats, int64_t* t1, int64_t* t2,
+                                    const float** x1, const float** x2, float** k, float** km) {
+  int64_t ia, ib;
+  if (a.tiles == nullptr) {
+    pair_of(p, a.n1, a.n2, a.sym, a.T, &ia, &ib);
+    *t1 = ia;
+    *t2 = ib;
+    *x1 = a.x1 + ia * img_floats;
+    *x2 = a.x2 + ib * img_floats;
+    *k = a.K ? a.K + ia * a.ldk + ib : nullptr;
+    *km = (a.K && a.sym && ia != ib) ? a.K + ib * a.ldk + ia : nullptr;
+    return;
+  }
+  int lo = 0, hi = a.ntiles - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.tiles[mid].p_begin <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const TileDesc& t = a.tiles[lo];
+  pair_of(p - t.p_begin, t.n1, t.n2, t.sym, a.T, &ia, &ib);
+  *t1 = t.t1 + ia;
+  *t2 = t.t2 + ib;
+  *x1 = t.x1 + ia * img_floats;
+  *x2 = t.x2 + ib * img_floats;
+  *k = t.K + ia * t.ldk + ib;
+  *km = (t.sym && ia != ib) ? t.K + ib * t.ldk + ia : nullptr;
+}
+
+// Work units (groups of PPWG consecutive pairs of the chunk) of this
+// workgroup.  Plain grid: one unit per workgroup, XCD-remapped.  Persistent
+// grid (a multiple of 8 workgroups, all resident): the dispatcher deals
+// workgroups round-robin over the 8 XCDs, so the workgroups of XCD x split
+// one contiguous eighth of the units between them and advance together: the
+// pairs in flight on an XCD at any time are neighbours in the pair order and
+// share images in that XCD's L2.
+__device__ inline void unit_range(int64_t nunits, int persist, int64_t* first, int64_t* step, int64_t* end) {
+  if (persist <= 0) {
+    *first = xcd_logical_block();
+    *step = nunits;
+    *end = *first + 1;
+    return;
+  }
+  const int64_t b = blockIdx.x, x = b & 7, s = b >> 3, per_xcd = gridDim.x >> 3;
+  const int64_t R = (nunits + 7) >> 3;
+  *first = x * R + s;
+  *step = per_xcd;
+  *end = (x + 1) * R < nunits ? (x + 1) * R : nunits;
+}
+
 template <int N, bool SEED, bool POOL, bool BIAS>
 __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs args) {
   constexpr int THREADS = KCfg<N>::THREADS, PPWG = KCfg<N>::PPWG;
   constexpr int H = N / 2;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ int64_t s_pa[PPWG], s_pb[PPWG];
+  __shared__ int64_t s_t1[PPWG], s_t2[PPWG];
+  __shared__ const float* s_x1[PPWG];
+  __shared__ const float* s_x2[PPWG];
+  __shared__ float* s_k[PPWG];
+  __shared__ float* s_km[PPWG];
 
   const int tid = threadIdx.x;
   const int slot = tid / (N * N);
@@ -54,22 +114,23 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
   const size_t slot_bytes = slot_lds_bytes<N>(D, POOL, SEED);
   const int TL = D * N * N;
 
-  const int64_t wg = xcd_logical_block();
+  const int64_t nunits = (args.np + PPWG - 1) / PPWG;
+  int64_t unit, ustep, uend;
+  unit_range(nunits, args.persist, &unit, &ustep, &uend);
+  for (; unit < uend; unit += ustep) {
   if (tid < PPWG) {
-    int64_t pl = wg * PPWG + tid;
+    int64_t pl = unit * PPWG + tid;
     if (pl >= args.np) pl = args.np - 1;
-    int64_t a, b;
-    pair_of(args.p0 + pl, args.n1, args.n2, args.sym, args.T, &a, &b);
-    s_pa[tid] = a;
-    s_pb[tid] = b;
+    resolve_pair(args, args.p0 + pl, (int64_t)N * N * args.C, &s_t1[tid], &s_t2[tid], &s_x1[tid], &s_x2[tid],
+                 &s_k[tid], &s_km[tid]);
   }
   __syncthreads();
   // this stage's (alpha, beta) tables of both images -> LDS; x2's rows twice
   for (int e = tid; e < PPWG * TL; e += THREADS) {
     const int s = e / TL, r = e - s * TL;
     float2* d1 = reinterpret_cast<float2*>(smem + s * slot_bytes);
-    d1[r] = args.tab1[s_pa[s] * args.tablen + args.taboff + r];
-    const float2 v = args.tab2[s_pb[s] * args.tablen + args.taboff + r];
+    d1[r] = args.tab1[s_t1[s] * args.tablen + args.taboff + r];
+    const float2 v = args.tab2[s_t2[s] * args.tablen + args.taboff + r];
     const int l = r / (N * N), rr = r - l * N * N;
     float2* d2 = d1 + TL + l * 2 * N * N;
     d2[rr] = v;
@@ -81,8 +142,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
     for (int e = tid; e < PPWG * N * N; e += THREADS) {
       const int s = e / (N * N), px = e - s * (N * N);
       float4* d = reinterpret_cast<float4*>(smem + s * slot_bytes + (size_t)TL * 24 + (rb < 16 ? 16 : rb));
-      const float* p1 = args.x1 + (s_pa[s] * (int64_t)N * N + px) * args.C;
-      const float* p2 = args.x2 + (s_pb[s] * (int64_t)N * N + px) * args.C;
+      const float* p1 = s_x1[s] + px * args.C;
+      const float* p2 = s_x2[s] + px * args.C;
       float u[4] = {0.f, 0.f, 0.f, 0.f}, w[4] = {0.f, 0.f, 0.f, 0.f};
       for (int c = 0; c < args.C && c < 4; ++c) {
         u[c] = p1[c];
@@ -94,9 +155,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
   }
   __syncthreads();
 
-  const int64_t pl = wg * PPWG + slot;
+  const int64_t pl = unit * PPWG + slot;
   const bool valid = pl < args.np;
-  const int64_t pa = s_pa[slot], pb = s_pb[slot];
   const float2* t1 = reinterpret_cast<const float2*>(smem + slot * slot_bytes);
   const float2* t2 = t1 + TL;
   float* red = reinterpret_cast<float*>(smem + slot * slot_bytes + (size_t)TL * 24);
@@ -228,16 +288,16 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
       double t = 0.0;
       for (int e = 0; e < N * N; ++e) t += part[e];
       const float kv = (float)(t + (double)args.sb2);
-      args.K[pa * args.ldk + pb] = kv;
-      if (args.sym && pa != pb) args.K[pb * args.ldk + pa] = kv;
+      *s_k[slot] = kv;
+      if (s_km[slot]) *s_km[slot] = kv;
     }
   }
+  __syncthreads();  // LDS and the slot table are reused by the next unit
+  }  // units of this workgroup
 }
 
 template <int N, bool SEED, bool POOL, bool BIAS>
-static int launch_t(const StageArgs& a, hipStream_t stream) {
-  const int64_t nwg = (a.np + KCfg<N>::PPWG - 1) / KCfg<N>::PPWG;
-  const size_t lds = (size_t)KCfg<N>::PPWG * slot_lds_bytes<N>(a.D, POOL, SEED);
+static int set_attr(size_t lds) {
   auto fn = stage_kernel<N, SEED, POOL, BIAS>;
   if (lds > 64 * 1024) {
     static size_t attr_bytes = 0;  // per instantiation
@@ -247,8 +307,57 @@ static int launch_t(const StageArgs& a, hipStream_t stream) {
       attr_bytes = lds;
     }
   }
-  hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(KCfg<N>::THREADS), lds, stream, a);
+  return 0;
+}
+
+template <int N, bool SEED, bool POOL, bool BIAS>
+static int launch_t(const StageArgs& a, hipStream_t stream) {
+  const int64_t nwg = (a.np + KCfg<N>::PPWG - 1) / KCfg<N>::PPWG;
+  const size_t lds = (size_t)KCfg<N>::PPWG * slot_lds_bytes<N>(a.D, POOL, SEED);
+  if (set_attr<N, SEED, POOL, BIAS>(lds)) return -3;
+  const int64_t grid = a.persist > 0 ? a.persist : nwg;
+  hipLaunchKernelGGL((stage_kernel<N, SEED, POOL, BIAS>), dim3((unsigned)grid), dim3(KCfg<N>::THREADS), lds, stream,
+                     a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int N, bool SEED, bool POOL, bool BIAS>
+static int occ_t(int D) {
+  const size_t lds = (size_t)KCfg<N>::PPWG * slot_lds_bytes<N>(D, POOL, SEED);
+  if (set_attr<N, SEED, POOL, BIAS>(lds)) return -3;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<N, SEED, POOL, BIAS>, KCfg<N>::THREADS, lds) !=
+      hipSuccess)
+    return -3;
+  return nb;
+}
+
+template <int N>
+static int occ_n(int D, bool seed, bool pool, bool bias) {
+  if (seed) {
+    if (pool) return bias ? occ_t<N, true, true, true>(D) : occ_t<N, true, true, false>(D);
+    return bias ? occ_t<N, true, false, true>(D) : occ_t<N, true, false, false>(D);
+  }
+  if (pool) return bias ? occ_t<N, false, true, true>(D) : occ_t<N, false, true, false>(D);
+  return bias ? occ_t<N, false, false, true>(D) : occ_t<N, false, false, false>(D);
+}
+
+// Resident workgroups per CU of a stage kernel (and sets its LDS attribute,
+// so that a later launch makes no attribute call, e.g. under graph capture).
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias) {
+  switch (N) {
+    case 2: return occ_n<2>(D, seed, pool, bias);
+    case 4: return occ_n<4>(D, seed, pool, bias);
+    case 8: return occ_n<8>(D, seed, pool, bias);
+    case 16: return occ_n<16>(D, seed, pool, bias);
+    case 32: return occ_n<32>(D, seed, pool, bias);
+  }
+  return -2;
+}
+
+int prime_stage(int N, int D, bool seed, bool pool, bool bias) {
+  const int r = stage_occupancy(N, D, seed, pool, bias);
+  return r < 0 ? r : 0;
 }
 
 template <int N>
@@ -259,6 +368,30 @@ static int launch_n(const StageArgs& a, bool seed, bool pool, bool bias, hipStre
   }
   if (pool) return bias ? launch_t<N, false, true, true>(a, s) : launch_t<N, false, true, false>(a, s);
   return bias ? launch_t<N, false, false, true>(a, s) : launch_t<N, false, false, false>(a, s);
+}
+
+// Tile table of a batched pass -> device memory through kernel arguments
+// (32 descriptors per launch): the arguments are copied at launch, so the
+// host array may go away at once, and the launches can be captured.
+struct TileBatch {
+  int n, pad;
+  TileDesc d[32];
+};
+
+__global__ void put_tiles_kernel(const TileBatch b, TileDesc* __restrict__ dst) {
+  if ((int)threadIdx.x < b.n) dst[threadIdx.x] = b.d[threadIdx.x];
+}
+
+int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t stream) {
+  for (int i = 0; i < n; i += 32) {
+    TileBatch b;
+    b.n = n - i < 32 ? n - i : 32;
+    b.pad = 0;
+    for (int k = 0; k < b.n; ++k) b.d[k] = host[i + k];
+    hipLaunchKernelGGL(put_tiles_kernel, dim3(1), dim3(32), 0, stream, b, dst + i);
+    if (hipGetLastError() != hipSuccess) return -3;
+  }
+  return 0;
 }
 
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed) {

@@ -174,3 +174,74 @@ def krr_mse_backward(k_ss: torch.Tensor, k_ts: torch.Tensor, y_s: torch.Tensor, 
                                         _stream(k_ss.device))
     _lib.check(rc)
     return dss, dts, float(loss.value), float(lam.value)
+
+
+def myrtle_nngp_batched(tiles, depth: Sequence[int], sigma_w2: float = 2.0, sigma_b2: float = 0.0,
+                        graph: bool = False, ws: torch.Tensor | None = None):
+    """Many Myrtle Gram tiles in one scheduled pass.  `tiles` is a list of
+    (x1, x2_or_None, out) with out a float32 (n1, >= n2) CUDA tensor whose
+    rows receive K[a, b] = k(x1[a], x2[b]) (x2 None: the symmetric x1 x x1
+    tile).  Tiles passing the same x tensor share its variance tables."""
+    if not tiles:
+        raise ValueError("no tiles")
+    arr = (_lib.Tile * len(tiles))()
+    hw = c = None
+    dev = None
+    for i, (x1, x2, out) in enumerate(tiles):
+        _check_images(x1, "x1")
+        if x2 is None:
+            x2 = x1
+        else:
+            _check_images(x2, "x2")
+        if x2.shape[1:] != x1.shape[1:] or (hw is not None and (x1.shape[1], x1.shape[3]) != (hw, c)):
+            raise ValueError("all tiles must use images of one shape")
+        hw, c = x1.shape[1], x1.shape[3]
+        dev = x1.device
+        if out.dtype != torch.float32 or not out.is_cuda or out.dim() != 2 or out.stride(1) != 1:
+            raise TypeError("out must be a row-major float32 CUDA matrix")
+        if out.shape[0] < x1.shape[0] or out.shape[1] < x2.shape[0]:
+            raise ValueError("out is smaller than the tile")
+        arr[i].x1 = x1.data_ptr()
+        arr[i].x2 = x2.data_ptr()
+        arr[i].n1 = x1.shape[0]
+        arr[i].n2 = x2.shape[0]
+        arr[i].K = out.data_ptr()
+        arr[i].ldk = out.stride(0)
+    cfg = _lib.myrtle_cfg(hw, c, depth, sigma_w2, sigma_b2)
+    L = _lib.lib()
+    if ws is None:
+        need = int(L.nk_myrtle_nngp_batched_workspace(arr, len(tiles), ctypes.byref(cfg)))
+        if need == 0:
+            _lib.check(L.nk_myrtle_nngp_batched(arr, len(tiles), ctypes.byref(cfg), None, 0, None, 0))
+        ws = workspace(need, dev)
+    rc = L.nk_myrtle_nngp_batched(arr, len(tiles), ctypes.byref(cfg), ws.data_ptr(), ws.numel(), _stream(dev),
+                                  1 if graph else 0)
+    _lib.check(rc)
+
+
+def batched_workspace_size(tiles, depth: Sequence[int], sigma_w2: float = 2.0, sigma_b2: float = 0.0) -> int:
+    arr = (_lib.Tile * len(tiles))()
+    for i, (x1, x2, out) in enumerate(tiles):
+        x2 = x1 if x2 is None else x2
+        arr[i].x1, arr[i].x2 = x1.data_ptr(), x2.data_ptr()
+        arr[i].n1, arr[i].n2 = x1.shape[0], x2.shape[0]
+        arr[i].K, arr[i].ldk = out.data_ptr(), out.stride(0)
+    x1 = tiles[0][0]
+    cfg = _lib.myrtle_cfg(x1.shape[1], x1.shape[3], depth, sigma_w2, sigma_b2)
+    return int(_lib.lib().nk_myrtle_nngp_batched_workspace(arr, len(tiles), ctypes.byref(cfg)))
+
+
+def batched_tuning(hw: int, c: int, depth: Sequence[int], sigma_w2: float = 2.0, sigma_b2: float = 0.0):
+    """(candidates, chosen) of the batched schedule tuned for this network, as
+    lists of dicts; raises if no batched pass has run for it yet."""
+    cfg = _lib.myrtle_cfg(hw, c, depth, sigma_w2, sigma_b2)
+    buf = (_lib.BatchedCandidate * 64)()
+    ch = _lib.BatchedCandidate()
+    n = _lib.lib().nk_myrtle_batched_tuning(ctypes.byref(cfg), buf, 64, ctypes.byref(ch))
+    if n < 0:
+        _lib.check(n)
+
+    def d(x):
+        return {"chunk": int(x.chunk), "pair_tile": int(x.pair_tile), "persistent": int(x.persistent),
+                "us_per_pair": float(x.us_per_pair)}
+    return [d(buf[i]) for i in range(min(n, 64))], d(ch)

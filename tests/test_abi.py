@@ -86,3 +86,32 @@ def test_fc_and_krr_validation():
     assert L.nk_krr_predict(p, 0, p, 4, p, 10, 1e-4, p, p, 1 << 30, None) == _lib.NK_EINVAL
     assert L.nk_krr_predict(p, 10, p, 4, p, 10, -1.0, p, p, 1 << 30, None) == _lib.NK_EINVAL
     assert L.nk_krr_predict(p, 10, p, 4, p, 10, 1e-4, p, p, 64, None) == _lib.NK_EINVAL
+
+
+def test_batched_validation():
+    L = _lib.lib()
+    cfg = _cfg()
+    p = ctypes.c_void_p(256)
+    tiles = (_lib.Tile * 2)()
+    for t in tiles:
+        t.x1 = t.x2 = t.K = 256
+        t.n1, t.n2, t.ldk = 5, 7, 7
+    need = L.nk_myrtle_nngp_batched_workspace(tiles, 2, ctypes.byref(cfg))
+    assert need > 0
+    assert L.nk_myrtle_nngp_batched_workspace(tiles, 0, ctypes.byref(cfg)) == 0
+    assert L.nk_myrtle_nngp_batched(None, 2, ctypes.byref(cfg), p, need, None, 0) == _lib.NK_EINVAL
+    assert L.nk_myrtle_nngp_batched(tiles, 0, ctypes.byref(cfg), p, need, None, 0) == _lib.NK_EINVAL
+    assert L.nk_myrtle_nngp_batched(tiles, 2, ctypes.byref(cfg), None, need, None, 0) == _lib.NK_EINVAL
+    assert L.nk_myrtle_nngp_batched(tiles, 2, ctypes.byref(cfg), p, 64, None, 0) == _lib.NK_EINVAL
+    assert "workspace" in L.nk_last_error().decode()
+    tiles[1].ldk = 6  # < n2
+    assert L.nk_myrtle_nngp_batched(tiles, 2, ctypes.byref(cfg), p, need, None, 0) == _lib.NK_EINVAL
+    tiles[1].ldk = 7
+    tiles[0].n1 = 0
+    assert L.nk_myrtle_nngp_batched(tiles, 2, ctypes.byref(cfg), p, need, None, 0) == _lib.NK_EINVAL
+    tiles[0].n1 = 5
+    tiles[0].K = None
+    assert L.nk_myrtle_nngp_batched(tiles, 2, ctypes.byref(cfg), p, need, None, 0) == _lib.NK_EINVAL
+    # no pass has been tuned in this process
+    out = (_lib.BatchedCandidate * 4)()
+    assert L.nk_myrtle_batched_tuning(ctypes.byref(cfg), out, 4, None) == _lib.NK_EINVAL

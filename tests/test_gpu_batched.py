@@ -1,0 +1,146 @@
+"""GPU tests of the batched uneven-tile pass (nk_myrtle_nngp_batched): every
+tile bitwise equal to the one-block entry point on the same tile, sampled
+entries of every tile against the FP64 oracle (normalised error <= 2e-5),
+shared image arrays with different prefixes, symmetric tiles, padded
+leading dimensions, the tuned schedule, and hipGraph capture with replays
+checked one by one against the eager pass."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_05420_amd import ops
+    return ops
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _tiles_from_shapes(pool_a, pool_b, shapes, sym_every=0, pad=0):
+    """Tiles over prefixes of two image pools: (x1 tensor view, x2 or None, out)."""
+    tiles = []
+    for t, (n1, n2) in enumerate(shapes):
+        if sym_every and t % sym_every == 0:
+            x1 = pool_a[:n1]
+            out = torch.full((n1, n1 + pad), float("nan"), device="cuda")
+            tiles.append((x1, None, out))
+        else:
+            out = torch.full((n1, n2 + pad), float("nan"), device="cuda")
+            tiles.append((pool_a[:n1], pool_b[:n2], out))
+    return tiles
+
+
+def _oracle_sample(xa, xb, tiles, depth, rng, per_tile):
+    """Oracle values at seeded entries of every tile: list of (tile, rows, cols, values, d1, d2)."""
+    net = oracle.Myrtle(depth)
+    qa, da = oracle.myrtle_self(xa, net)
+    qb, db = oracle.myrtle_self(xb, net)
+    res = []
+    for t, (x1, x2, out) in enumerate(tiles):
+        n1 = x1.shape[0]
+        n2 = n1 if x2 is None else x2.shape[0]
+        r = rng.integers(0, n1, per_tile)
+        c = rng.integers(0, n2, per_tile)
+        if x2 is None:
+            v = oracle.myrtle_pairs(xa, xa, np.stack([r, c], 1), net, qa, qa)
+            res.append((t, r, c, v, da[r], da[c]))
+        else:
+            v = oracle.myrtle_pairs(xa, xb, np.stack([r, c], 1), net, qa, qb)
+            res.append((t, r, c, v, da[r], db[c]))
+    return res
+
+
+def test_batched_small_uneven_tiles_match_plain_and_oracle(nk):
+    depth = (2, 1, 1)
+    xa_n = synth.iid_images(80, 8, 8, 3, 11)
+    xb_n = synth.iid_images(70, 8, 8, 3, 12)
+    xa, xb = _gpu(xa_n), _gpu(xb_n)
+    shapes = [(17, 40), (1, 1), (64, 3), (80, 70), (33, 33), (5, 69), (40, 17), (80, 1)]
+    tiles = _tiles_from_shapes(xa, xb, shapes, sym_every=3, pad=5)
+    _say(f"batched 8x8 Myrtle-5: {len(tiles)} tiles")
+    nk.myrtle_nngp_batched(tiles, depth)
+    torch.cuda.synchronize()
+    for t, (x1, x2, out) in enumerate(tiles):
+        n2 = x1.shape[0] if x2 is None else x2.shape[0]
+        ref = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+        got = out[:, :n2].cpu().numpy()
+        assert np.array_equal(got, ref), f"tile {t} differs from the one-block entry point"
+        assert torch.isnan(out[:, n2:]).all(), f"tile {t} wrote past n2"
+    rng = np.random.default_rng(13)
+    for t, r, c, v, d1, d2 in _oracle_sample(xa_n, xb_n, tiles, depth, rng, 6):
+        got = tiles[t][2].cpu().numpy()[r, c]
+        err = float(np.max(np.abs(got - v) / np.sqrt(d1 * d2)))
+        assert err <= TOL, f"tile {t}: {err:.2e}"
+    cands, chosen = nk.batched_tuning(8, 3, depth)
+    _say(f"  tuned: {chosen} of {len(cands)} candidates")
+    assert len(cands) >= 2
+    assert any(c["chunk"] == chosen["chunk"] and c["pair_tile"] == chosen["pair_tile"]
+               and c["persistent"] == chosen["persistent"] for c in cands)
+
+
+def test_batched_graph_replays_match_eager(nk):
+    depth = (2, 2, 2)
+    xa = _gpu(synth.correlated_images(48, 16, 16, 3, 2.0, 21))
+    xb = _gpu(synth.correlated_images(40, 16, 16, 3, 2.0, 22))
+    tiles = _tiles_from_shapes(xa, xb, [(48, 40), (7, 39), (30, 30), (48, 1), (12, 12)], sym_every=2)
+    _say("batched 16x16 Myrtle-7 eager")
+    nk.myrtle_nngp_batched(tiles, depth, graph=False)
+    torch.cuda.synchronize()
+    eager = [o.clone() for _, _, o in tiles]
+    for rep in range(3):
+        for _, _, o in tiles:
+            o.fill_(float("nan"))
+        _say(f"  graph pass {rep}")
+        nk.myrtle_nngp_batched(tiles, depth, graph=True)
+        torch.cuda.synchronize()
+        # eager work on the same stream between replays
+        junk = nk.myrtle_nngp(xa[:9], xb[:4], depth)
+        torch.cuda.synchronize()
+        del junk
+        for t, (_, _, o) in enumerate(tiles):
+            assert torch.equal(o, eager[t]), f"replay {rep}, tile {t} differs from the eager pass"
+
+
+def test_batched_uneven_myrtle7_32x32_sample(nk):
+    """The uneven-tile workload at reduced tile sides (U{32..256} instead of
+    U{32..2048}; same generator, pools and network), >= 4 oracle entries per
+    tile and bitwise agreement with the one-block entry point."""
+    w = synth.WORKLOADS["myrtle7_uneven64"]
+    depth = w["depth"]
+    n_tiles = 16
+    shapes = synth.uneven_tile_shapes(n_tiles, 32, 256, w["seeds"][2])
+    pa = synth.correlated_images(256, 32, 32, 3, w["length"], w["seeds"][0])
+    pb = synth.correlated_images(256, 32, 32, 3, w["length"], w["seeds"][1])
+    xa, xb = _gpu(pa), _gpu(pb)
+    tiles = _tiles_from_shapes(xa, xb, [tuple(int(v) for v in s) for s in shapes])
+    _say(f"batched 32x32 Myrtle-7: {n_tiles} tiles, {sum(int(a) * int(b) for a, b in shapes)} pairs")
+    nk.myrtle_nngp_batched(tiles, depth)
+    torch.cuda.synchronize()
+    for t in (0, 5, 11):
+        x1, x2, out = tiles[t]
+        ref = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+        assert np.array_equal(out.cpu().numpy(), ref)
+    rng = np.random.default_rng(w["seeds"][2] + 1)
+    for t, r, c, v, d1, d2 in _oracle_sample(pa, pb, tiles, depth, rng, 4):
+        got = tiles[t][2].cpu().numpy()[r, c]
+        err = float(np.max(np.abs(got - v) / np.sqrt(d1 * d2)))
+        assert err <= TOL, f"tile {t}: {err:.2e}"
