@@ -41,6 +41,9 @@ def _args():
     p.add_argument("--copy-calib-mib", type=int, default=0,
                    help="also run a plain device copy of this many MiB (counter calibration runs)")
     p.add_argument("--no-fwd-bwd", action="store_true", help="skip the fwd+bwd measurement")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain tile comparison")
+    p.add_argument("--batched-full", action="store_true",
+                   help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
 
 
@@ -103,6 +106,53 @@ def _fwd_bwd(torch):
             "loss": loss, "dsigma": [float(v) for v in ds.cpu().tolist()],
             "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
             "stage_kernels_fwd_ms": round(fwd_ms, 3), "stage_kernels_bwd_ms": round(bwd_ms, 3)}
+
+
+def _batched(torch, full: bool):
+    """Uneven Myrtle-7 tiles at 32x32x3: one batched pass (tuned schedule,
+    hipGraph) against the plain form (one nk_myrtle_nngp call per tile), both
+    timed once after one untimed pass; the outputs are compared bitwise."""
+    import numpy as np
+
+    import synth
+    from paper_2303_05420_amd import ops
+
+    w = synth.WORKLOADS["myrtle7_uneven64"]
+    depth = w["depth"]
+    hi = w["hi"] if full else 512
+    pool = w["pool"] if full else 512
+    shapes = synth.uneven_tile_shapes(w["n_tiles"], w["lo"], hi, w["seeds"][2])
+    xa = torch.from_numpy(synth.correlated_images(pool, 32, 32, 3, w["length"], w["seeds"][0])).cuda()
+    xb = torch.from_numpy(synth.correlated_images(pool, 32, 32, 3, w["length"], w["seeds"][1])).cuda()
+    outs_b = [torch.empty((int(a), int(b)), dtype=torch.float32, device="cuda") for a, b in shapes]
+    outs_p = [torch.empty_like(o) for o in outs_b]
+    tiles = [(xa[:int(a)], xb[:int(b)], o) for (a, b), o in zip(shapes, outs_b)]
+    pairs = int(sum(int(a) * int(b) for a, b in shapes))
+
+    def plain():
+        for (a, b), o in zip(shapes, outs_p):
+            ops.myrtle_nngp(xa[:int(a)], xb[:int(b)], depth, out=o)
+
+    def batched():
+        ops.myrtle_nngp_batched(tiles, depth, graph=True)
+
+    res = {}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        fn()
+        torch.cuda.synchronize()
+        print(f"{name} tiles: warm-up done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        res[name] = time.perf_counter() - t0
+        print(f"{name} tiles: {res[name]:.2f} s", file=sys.stderr, flush=True)
+    same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_p))
+    cands, chosen = ops.batched_tuning(32, 3, depth)
+    return {"workload": f"Myrtle-7 NNGP at 32x32x3, {len(shapes)} tiles with sides U{{{w['lo']}..{hi}}} "
+                        f"over prefixes of two pools of {pool} images",
+            "pairs": pairs, "batched_pairs_per_s": round(pairs / res["batched"], 1),
+            "plain_pairs_per_s": round(pairs / res["plain"], 1), "speedup": round(res["plain"] / res["batched"], 4),
+            "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands)}
 
 
 def main():
@@ -189,6 +239,7 @@ def main():
     whole = flops_pair * pairs / (ms_step / 1e3) / 1e12
 
     fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
+    batched = None if a.no_batched else _batched(torch, a.batched_full)
 
     cpu = None
     parity = None
@@ -235,6 +286,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "fwd_bwd": fwd_bwd,
+        "batched_tiles": batched,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))

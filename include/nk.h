@@ -67,7 +67,8 @@ enum { NK_OP_FC = 0, NK_OP_MYRTLE = 1, NK_OP_MYRTLE_BWD = 2, NK_OP_KRR = 3, NK_O
  *
  * Supported: H == W a power of two with 2 <= H <= 32 and every stage at
  * least 2 x 2 (H >> (n_stages-1) >= 2), filter == 3, 1 <= n_stages <= 4,
- * 0 <= depth[s] <= 4 with depth[0] >= 1, 1 <= C <= 4,
+ * 0 <= depth[s] <= 4 with depth[0] >= 1 (depth[0] <= 3 when H == 32: the
+ * first stage keeps its tables and both images in LDS), 1 <= C <= 4,
  * sigma_w2 > 0, sigma_b2 >= 0.  Anything else returns NK_EUNSUPPORTED
  * (or NK_EINVAL for values that define no network).
  */

@@ -5,7 +5,7 @@ For cos t = rho in [0, 1] write u = 1 - rho.  The normalised map
 J1(rho) = (sin t + (pi - t) rho) / pi satisfies J1 = rho + u^{3/2} H(u) with H
 analytic on [0, 1] (H(0) = 2 sqrt(2) / (3 pi)): sin t - t cos t is t^3 times
 an even series and t^2 is u times an analytic series.  H is fitted by a
-polynomial of degree 5 minimising the maximum relative error of J1 (weight
+polynomial of degree 4 minimising the maximum relative error of J1 (weight
 u^{3/2} / J1), using Lawson's iteratively reweighted least squares on 4000
 Chebyshev points, with H evaluated in 40-digit arithmetic.  Negative rho uses
 J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
@@ -21,7 +21,7 @@ import mpmath as mp
 import numpy as np
 
 
-def main(degree: int = 5, m: int = 4000):
+def main(degree: int = 4, m: int = 4000):
     mp.mp.dps = 40
 
     def j1(rho):

@@ -89,6 +89,8 @@ constexpr int kPairTile = 16;           // images per side of a pair-order tile
 constexpr int64_t kDefaultChunk = 16384;  // pairs per stage pass for workspace queries
 constexpr int64_t kPrepBlocks = 2048;     // images prepared per launch
 
+constexpr size_t kLdsDynamicMax = 160 * 1024 - 1024;  // dynamic LDS per workgroup
+
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
@@ -117,7 +119,8 @@ int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
   for (int s = 0; s < net->S; ++s) {
     const int N = net->hw >> s;
     const bool seed = s == 0, pool = s + 1 < net->S;
-    if (nk::stage_lds_bytes(N, net->depth[s], pool, seed) > 160 * 1024)
+    // 160 KiB per workgroup, less 1 KiB for the kernels' static LDS
+    if (nk::stage_lds_bytes(N, net->depth[s], pool, seed) > kLdsDynamicMax)
       return fail(NK_EUNSUPPORTED, "stage %d needs more than 160 KiB of LDS", s);
   }
   return NK_OK;
@@ -662,7 +665,7 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
   const bool sym = (x1 == x2) && (n1 == n2);
   if (sym && dx2 && dx2 != dx1) return fail(NK_EINVAL, "symmetric block: dx2 must be NULL or equal to dx1");
   for (int s = 0; s < net.S; ++s)
-    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0) > 160 * 1024)
+    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0) > kLdsDynamicMax)
       return fail(NK_EUNSUPPORTED, "adjoint of stage %d needs more than 160 KiB of LDS", s);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   const int64_t chunk = max_chunk_bwd(net, n1, n2, sym, ws_bytes, npairs);

@@ -5,16 +5,16 @@
 
 // ReLU arc-cosine map, normalised: J1(rho) = (sin t + (pi - t) rho) / pi with
 // cos t = rho, written as J1 = rho + u^{3/2} H(u), u = 1 - rho.  H is our own
-// degree-5 weighted-minimax polynomial fit on [0, 1] (gen_relu_poly.py; max
-// relative error of J1 1.5e-8 in exact arithmetic).  Then
+// degree-4 weighted-minimax polynomial fit on [0, 1] (gen_relu_poly.py; max
+// relative error of J1 1.3e-7 in exact arithmetic, about two float32
+// roundings).  Then
 //   E[relu(a) relu(b)] = sqrt(q q') / 2 * J1(s / sqrt(q q'))
 // for (a, b) ~ N(0, [[q, s], [s, q']]).
-#define NK_J1_C0 0.30010318756103516f
-#define NK_J1_C1 0.015035496093332767f
-#define NK_J1_C2 0.002265139250084758f
-#define NK_J1_C3 0.0008933312492445111f
-#define NK_J1_C4 -0.00022516770695801824f
-#define NK_J1_C5 0.00023788731778040528f
+#define NK_J1_C0 0.30011793971061707f
+#define NK_J1_C1 0.014882231131196022f
+#define NK_J1_C2 0.0028328807093203068f
+#define NK_J1_C3 -7.56633744458668e-05f
+#define NK_J1_C4 0.0005524527514353395f
 
 // acos(1 - u) = sqrt(u) G(u); G is our own degree-6 fit on [0, 1]
 // (gen_relu_poly.py; dJ1/drho = 1 - acos(rho)/pi to 2.8e-8).
@@ -132,8 +132,7 @@ __device__ __forceinline__ int opaque_zero() {
 }
 
 __device__ __forceinline__ float relu_poly(float u) {
-  float p = NK_J1_C5;
-  p = __builtin_fmaf(p, u, NK_J1_C4);
+  float p = NK_J1_C4;
   p = __builtin_fmaf(p, u, NK_J1_C3);
   p = __builtin_fmaf(p, u, NK_J1_C2);
   p = __builtin_fmaf(p, u, NK_J1_C1);
@@ -142,11 +141,22 @@ __device__ __forceinline__ float relu_poly(float u) {
 }
 
 // J1 for rho >= 0 (every ReLU after the first: inputs are sums of
-// non-negative terms).  u is clamped to [0, 1].
+// non-negative terms), as 1 - u (1 - sqrt(u) H(u)) with u = 1 - rho clamped to
+// [0, 1] (two FMAs after the polynomial; rho > 1 from rounding gives J1(1) = 1).
 __device__ __forceinline__ float j1_nonneg(float rho) {
   float u = __builtin_amdgcn_fmed3f(1.0f - rho, 0.0f, 1.0f);
   float sq = __builtin_amdgcn_sqrtf(u);
-  return __builtin_fmaf(u * sq, relu_poly(u), rho);
+  return __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), 1.0f);
+}
+
+// J1 of rho = v rr for rho in [-1, 1] (rr > 0): J1(rho) = J1(|rho|) - |rho|
+// for rho < 0, i.e. 1 - u (1 - sqrt(u) H(u)) + min(rho, 0) with u = 1 - |rho|;
+// both u and 1 + min(rho, 0) = clamp(1 + rho) come out of one clamped FMA each.
+__device__ __forceinline__ float j1_signed_vr(float v, float rr) {
+  const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-__builtin_fabsf(v), rr, 1.0f), 0.0f, 1.0f);
+  const float c = __builtin_amdgcn_fmed3f(__builtin_fmaf(v, rr, 1.0f), 0.0f, 1.0f);
+  const float sq = __builtin_amdgcn_sqrtf(u);
+  return __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), c);
 }
 
 // J1 for rho in [-1, 1]: J1(rho) = J1(|rho|) - |rho| for rho < 0.

@@ -13,18 +13,30 @@ struct KCfg {
 };
 
 // LDS per pair: [tables x1: D N^2 float2][tables x2, rows twice: 2 D N^2 float2]
-// [pooling row / readout partials][images as float4 (seeding stage only)]
+// [pooling row / readout partials][images as float4 (seeding stage only):
+// x1, then x2 with its rows twice]
 template <int N>
 __host__ __device__ inline size_t slot_lds_bytes(int D, bool pool, bool seed) {
-  size_t t = (size_t)D * N * N * 8 + (size_t)D * 2 * N * N * 8 + (seed ? (size_t)2 * N * N * 16 : 0);
+  size_t t = (size_t)D * N * N * 8 + (size_t)D * 2 * N * N * 8 + (seed ? (size_t)3 * N * N * 16 : 0);
   size_t r = pool ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
   if (r < 16) r = 16;
   return (t + r + 15) & ~(size_t)15;
 }
 
-// masked 3-tap sum along the lanes of a segment
+// Masked 3-tap sum along the lanes of a segment,
+//   x + x(lane - 1) mL + x(lane + 1) mR   (0 past the ends of the wave),
+// with each lane shift fused into its FMA as a DPP source operand (the
+// compiler keeps DPP moves separate from FMAs).  The s_nop gives the two
+// wait states a DPP source needs after a VALU write to it.
 __device__ __forceinline__ float hsum3(float x, float mL, float mR) {
-  return (x + lane_prev(x) * mL) + lane_next(x) * mR;
+  float h;
+  asm("v_mov_b32 %0, %1\n\t"
+      "s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %1, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %1, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(h)
+      : "v"(x), "v"(mL), "v"(mR));
+  return h;
 }
 
 // wave-uniform 0/1 factor (kept in a scalar register)
@@ -49,8 +61,8 @@ __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restri
     if (BIAS) v += sb2;
     const float2 a = c1[r * N];
     const float2 b = c2[r * N];
-    const float rho = v * (a.x * b.x);
-    const float J = SIGNED ? j1_signed(rho) : j1_nonneg(rho);
+    const float rr = a.x * b.x;
+    const float J = SIGNED ? j1_signed_vr(v, rr) : j1_nonneg(v * rr);
     A[r] = (a.y * b.y) * J;
     hm = h0;
     h0 = hp;

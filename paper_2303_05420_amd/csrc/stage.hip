@@ -149,8 +149,13 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
         u[c] = p1[c];
         w[c] = p2[c];
       }
+      // the seed scale sigma_w2 / (9 C) rides on the second image
+      const float sc = args.seed_scale;
+      // (the second image twice, so that its rows are read without wrapping)
       d[px] = make_float4(u[0], u[1], u[2], u[3]);
-      d[N * N + px] = make_float4(w[0], w[1], w[2], w[3]);
+      const float4 ws = make_float4(sc * w[0], sc * w[1], sc * w[2], sc * w[3]);
+      d[N * N + px] = ws;
+      d[2 * N * N + px] = ws;
     }
   }
   __syncthreads();
@@ -184,10 +189,9 @@ __global__ __launch_bounds__(KCfg<N>::THREADS) void stage_kernel(const StageArgs
     if (SEED) {
 #pragma unroll
       for (int r = 0; r < N; ++r) {
-        const int jy = (r + ky) & (N - 1);
         const float4 u = img1[r * N + ix];
-        const float4 w = img2[jy * N + jx];
-        A[r] = args.seed_scale * __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
+        const float4 w = img2[(r + ky) * N + jx];
+        A[r] = __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
       }
     } else {
       const float* p = inp + ((int64_t)ky * N + kx) * N * N + ix;

@@ -46,6 +46,7 @@ def test_workspace_size_queries():
     (dict(sigma_b2=-1.0), _lib.NK_EINVAL),
     (dict(depth=(2, 5, 1)), _lib.NK_EUNSUPPORTED),
     (dict(hw=8, depth=(1, 1, 1, 1)), _lib.NK_EUNSUPPORTED),  # last stage 1 x 1
+    (dict(hw=32, depth=(4, 1, 1)), _lib.NK_EUNSUPPORTED),  # first-stage tables + images exceed LDS
 ])
 def test_myrtle_config_validation(kw, code):
     L = _lib.lib()
@@ -58,6 +59,16 @@ def test_myrtle_config_validation(kw, code):
                           ctypes.c_void_p(16), 1 << 20, None)
     assert rc == code, L.nk_last_error()
     assert L.nk_last_error().decode() != ""
+
+
+def test_depth4_first_stage_fits_below_32():
+    L = _lib.lib()
+    cfg = _cfg(hw=16, depth=(4, 1, 1))
+    assert L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 8, 8) > 0
+    cfg = _cfg(hw=32, depth=(3, 3, 3))
+    assert L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 8, 8) > 0
+    cfg = _cfg(hw=32, depth=(4, 1, 1))
+    assert L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 8, 8) == 0
 
 
 def test_myrtle_argument_validation():
