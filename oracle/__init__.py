@@ -9,6 +9,9 @@ Contents
 * ``myrtle_self`` / ``myrtle_pairs`` / ``myrtle_gram`` -- the Myrtle NNGP
   (App. A, Myrtle listing) as the plain float64 loop recursion in
   ``nk_oracle.c``.
+* ``myrtle_ntk_pairs`` / ``myrtle_ntk_gram`` -- the Myrtle neural tangent
+  kernel (the kernel of the paper's large-scale runs) with its NNGP, same C
+  file.
 * ``fc_nngp`` -- the FC3 NNGP (App. A, FC listing), same C file.
 * ``krr_predict`` -- kernel ridge regression, the linear system that the
   paper's conjugate-gradient solver targets (Sec. 2, iterative solvers),
@@ -65,6 +68,10 @@ def _load():
     lib.nko_fc_nngp.restype = ci
     lib.nko_relu_map.argtypes = [cd, cd, cd]
     lib.nko_relu_map.restype = cd
+    lib.nko_relu_dot.argtypes = [cd, cd, cd]
+    lib.nko_relu_dot.restype = cd
+    lib.nko_myrtle_ntk_pairs.argtypes = [P, P, P, P, ci, ci, ci, ci, P, cd, cd, P, i64, P, P, ci]
+    lib.nko_myrtle_ntk_pairs.restype = ci
     lib.nko_num_threads.argtypes = []
     lib.nko_num_threads.restype = ci
     _lib = lib
@@ -96,6 +103,11 @@ class Myrtle:
 def relu_map(s: float, q1: float, q2: float) -> float:
     """E[relu(u) relu(v)], (u, v) ~ N(0, [[q1, s], [s, q2]])."""
     return float(_load().nko_relu_map(float(s), float(q1), float(q2)))
+
+
+def relu_dot(s: float, q1: float, q2: float) -> float:
+    """E[relu'(u) relu'(v)], (u, v) ~ N(0, [[q1, s], [s, q2]])."""
+    return float(_load().nko_relu_dot(float(s), float(q1), float(q2)))
 
 
 def _check_images(x: np.ndarray) -> np.ndarray:
@@ -176,6 +188,55 @@ def myrtle_gram(x1: np.ndarray, x2: np.ndarray | None, net: Myrtle, threads: int
     a, b = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
     pairs = np.stack([a.ravel(), b.ravel()], axis=1)
     return myrtle_pairs(x1, x2, pairs, net, threads=threads).reshape(n1, n2)
+
+
+def myrtle_ntk_pairs(x1: np.ndarray, x2: np.ndarray, pairs: np.ndarray, net: Myrtle, q1=None, q2=None,
+                     threads: int | None = None):
+    """(NNGP, NTK) of (x1[a], x2[b]) for each row (a, b) of ``pairs`` (float64)."""
+    x1 = _check_images(x1)
+    x2 = _check_images(x2)
+    n1, h, w, c = x1.shape
+    if x2.shape[1:] != (h, w, c):
+        raise ValueError("image shapes differ")
+    pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+    if pairs.size and (pairs[:, 0].min() < 0 or pairs[:, 0].max() >= n1 or pairs[:, 1].min() < 0
+                       or pairs[:, 1].max() >= x2.shape[0]):
+        raise IndexError("pair index out of range")
+    thr = threads or default_threads()
+    ua, ia = np.unique(pairs[:, 0], return_inverse=True)
+    ub, ib = np.unique(pairs[:, 1], return_inverse=True)
+    q1s = myrtle_self(x1[ua], net, thr)[0] if q1 is None else np.ascontiguousarray(q1[ua])
+    q2s = myrtle_self(x2[ub], net, thr)[0] if q2 is None else np.ascontiguousarray(q2[ub])
+    xs1 = np.ascontiguousarray(x1[ua])
+    xs2 = np.ascontiguousarray(x2[ub])
+    local = np.ascontiguousarray(np.stack([ia, ib], axis=1).astype(np.int64))
+    kn = np.zeros(len(local), dtype=np.float64)
+    kt = np.zeros(len(local), dtype=np.float64)
+    d = np.ascontiguousarray(net.depth, dtype=np.int32)
+    rc = _load().nko_myrtle_ntk_pairs(_ptr(xs1), _ptr(q1s), _ptr(xs2), _ptr(q2s), h, w, c, net.n_stages, _ptr(d),
+                                      net.sigma_w2, net.sigma_b2, _ptr(local), len(local), _ptr(kn), _ptr(kt), thr)
+    if rc != 0:
+        raise ValueError(f"oracle nko_myrtle_ntk_pairs failed ({rc})")
+    return kn, kt
+
+
+def myrtle_ntk_gram(x1: np.ndarray, x2: np.ndarray | None, net: Myrtle, threads: int | None = None):
+    """(NNGP, NTK) Gram blocks (float64); ``x2 is None`` means x1 x x1."""
+    if x2 is None:
+        n = x1.shape[0]
+        iu = np.triu_indices(n)
+        kn, kt = myrtle_ntk_pairs(x1, x1, np.stack(iu, axis=1), net, threads=threads)
+        out = []
+        for v in (kn, kt):
+            K = np.zeros((n, n))
+            K[iu] = v
+            K[(iu[1], iu[0])] = v
+            out.append(K)
+        return out[0], out[1]
+    n1, n2 = x1.shape[0], x2.shape[0]
+    a, b = np.meshgrid(np.arange(n1), np.arange(n2), indexing="ij")
+    kn, kt = myrtle_ntk_pairs(x1, x2, np.stack([a.ravel(), b.ravel()], axis=1), net, threads=threads)
+    return kn.reshape(n1, n2), kt.reshape(n1, n2)
 
 
 def fc_nngp(x1: np.ndarray, x2: np.ndarray, depth: int = 3, sigma_w2: float = 2.0, sigma_b2: float = 0.01,

@@ -82,3 +82,46 @@ def myrtle_pair(x1: np.ndarray, x2: np.ndarray, depth: Sequence[int], sw2: float
             h, w = h // 2, w // 2
     n = h * w
     return float(sw2 * M[:n, n:].mean() + sb2)
+
+
+def _Fdot(s, q1, q2):
+    """E[relu'(u) relu'(v)] = (pi - t) / (2 pi), entry-wise."""
+    qq = q1 * q2
+    out = np.zeros_like(s)
+    pos = qq > 0
+    nrm = np.sqrt(np.where(pos, qq, 1.0))
+    rho = np.clip(s / nrm, -1.0, 1.0)
+    val = (math.pi - np.arccos(rho)) / (2 * math.pi)
+    out[pos] = val[pos]
+    return out
+
+
+def myrtle_pair_ntk(x1: np.ndarray, x2: np.ndarray, depth: Sequence[int], sw2: float, sb2: float):
+    """(NNGP, NTK) of one pair in the joint-matrix form: beside the covariance
+    M of the stacked pre-activations it carries their tangent-kernel matrix
+    Th; a conv maps the post-activation tangent matrix P to
+    Th = M_new + (sw2 / 9) sum_d T_d P T_d^T, a ReLU sets P = Fdot(M) * Th
+    entry-wise, pools act on P like on M, and the readout adds
+    sw2 * mean of P's cross block."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    h, w, c = x1.shape
+    X = np.concatenate([x1.reshape(h * w, c), x2.reshape(h * w, c)], axis=0)
+    M = X @ X.T / c
+    P = np.zeros_like(M)
+    for s, d in enumerate(depth):
+        T = [_blockdiag(_shift(h, w, dy, dx)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        for _ in range(d):
+            M = sw2 / 9.0 * sum(t @ M @ t.T for t in T) + sb2
+            Th = M + sw2 / 9.0 * sum(t @ P @ t.T for t in T)
+            q = np.diag(M).copy()
+            P = _Fdot(M, q[:, None], q[None, :]) * Th
+            M = _F(M, q[:, None], q[None, :])
+        if s + 1 < len(depth):
+            Q = _blockdiag(_avg2(h, w))
+            M = Q @ M @ Q.T
+            P = Q @ P @ Q.T
+            h, w = h // 2, w // 2
+    n = h * w
+    k = float(sw2 * M[:n, n:].mean() + sb2)
+    return k, k + float(sw2 * P[:n, n:].mean())

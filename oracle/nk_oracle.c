@@ -34,6 +34,22 @@
  * same layer, so every image first runs the full pair recursion against
  * itself.  All arithmetic is float64; inputs are the float32 arrays the GPU
  * reads, promoted once.
+ *
+ * Neural tangent kernel of the same Myrtle network (the kernel the paper's
+ * large-scale runs use, e.g. the 10-layer Myrtle NTK of the section on
+ * approaches to large-scale kernel methods), in the parameterisation where
+ * every layer scales its N(0,1) weights by sigma_w / sqrt(fan-in) and its
+ * N(0,1) biases by sigma_b.  Beside the covariance S of the pre-activations
+ * it carries their tangent kernel T (sum over all parameters below the layer
+ * of the products of derivatives), and beside A the post-activation tangent
+ * kernel B:
+ *   seed        B0 = 0 (the input has no parameters)
+ *   conv 3x3    T(i,j) = S(i,j) + (sw2/9) sum_d B(i+d, j+d)   (same padding
+ *                        rule; S already holds the weight and bias terms)
+ *   ReLU        B(i,j) = Fdot(S(i,j), q(i), q'(j)) T(i,j),
+ *               Fdot = E[relu'(u) relu'(v)] = (pi - t) / (2 pi)
+ *   avg pool    pools B like A
+ *   readout     Theta = K + sw2 * mean_{i,j} B(i,j)
  */
 #include <math.h>
 #include <stdint.h>
@@ -286,6 +302,145 @@ int nko_myrtle_pairs(const float* x1, const double* q1, const float* x2, const d
   }
   return err;
 }
+
+
+/* E[relu'(u) relu'(v)] for (u, v) ~ N(0, [[q1, s], [s, q2]]). */
+static double relu_dot(double s, double q1, double q2) {
+  double qq = q1 * q2;
+  if (!(qq > 0.0)) return 0.0;
+  double rho = s / sqrt(qq);
+  if (rho > 1.0) rho = 1.0;
+  if (rho < -1.0) rho = -1.0;
+  return (NKO_PI - acos(rho)) / (2.0 * NKO_PI);
+}
+
+/* T = S + (sw2/9) sum_d B(i+d, j+d), with the conv's padding rule. */
+static void conv_tangent4(const double* B, const double* S, double* T, int h, int w, double sw2) {
+  for (int iy = 0; iy < h; ++iy)
+    for (int ix = 0; ix < w; ++ix)
+      for (int jy = 0; jy < h; ++jy)
+        for (int jx = 0; jx < w; ++jx) {
+          double s = 0.0;
+          for (int dy = -1; dy <= 1; ++dy) {
+            int ay = iy + dy, by = jy + dy;
+            if (ay < 0 || ay >= h || by < 0 || by >= h) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+              int ax = ix + dx, bx = jx + dx;
+              if (ax < 0 || ax >= w || bx < 0 || bx >= w) continue;
+              s += B[IDX4(ay, ax, by, bx, h, w)];
+            }
+          }
+          size_t e = IDX4(iy, ix, jy, jx, h, w);
+          T[e] = S[e] + sw2 / 9.0 * s;
+        }
+}
+
+/* B = Fdot(S, q, q') * T */
+static void relu_tangent4(const double* S, const double* T, double* B, int h, int w, const double* q1,
+                          const double* q2) {
+  for (int iy = 0; iy < h; ++iy)
+    for (int ix = 0; ix < w; ++ix)
+      for (int jy = 0; jy < h; ++jy)
+        for (int jx = 0; jx < w; ++jx) {
+          size_t e = IDX4(iy, ix, jy, jx, h, w);
+          B[e] = relu_dot(S[e], q1[iy * w + ix], q2[jy * w + jx]) * T[e];
+        }
+}
+
+/*
+ * NNGP and NTK of one pair (cross mode: q1, q2 from the self recursion).
+ * buf0..buf4 hold H*W*H*W doubles each.
+ */
+static void myrtle_pair_ntk(const nko_myrtle* m, const double* x1, const double* x2, const double* q1,
+                            const double* q2, double* bufs[5], double* k_nngp, double* k_ntk) {
+  int h = m->H, w = m->W;
+  double* A = bufs[0];
+  double* B = bufs[1];
+  double* S = bufs[2];
+  double* T = bufs[3];
+  double* P = bufs[4];
+  seed4(x1, x2, h, w, m->C, A);
+  memset(B, 0, sizeof(double) * (size_t)h * w * h * w);
+  size_t qoff = 0;
+  for (int s = 0; s < m->n_stages; ++s) {
+    for (int l = 0; l < m->depth[s]; ++l) {
+      conv4(A, S, h, w, m->sw2, m->sb2);
+      conv_tangent4(B, S, T, h, w, m->sw2);
+      relu4(S, A, h, w, q1 + qoff, q2 + qoff);
+      relu_tangent4(S, T, B, h, w, q1 + qoff, q2 + qoff);
+      qoff += (size_t)h * w;
+    }
+    if (s + 1 < m->n_stages) {
+      pool4(A, P, h, w);
+      pool4(B, S, h, w);
+      double* t = A;
+      A = P;
+      P = t;
+      t = B;
+      B = S;
+      S = t;
+      h /= 2;
+      w /= 2;
+    }
+  }
+  size_t n4 = (size_t)h * w * h * w;
+  double ka = 0.0, kb = 0.0;
+  for (size_t e = 0; e < n4; ++e) {
+    ka += A[e];
+    kb += B[e];
+  }
+  *k_nngp = m->sw2 * (ka / (double)n4) + m->sb2;
+  *k_ntk = *k_nngp + m->sw2 * (kb / (double)n4);
+}
+
+/*
+ * NNGP and NTK for a list of (a, b) pairs (as nko_myrtle_pairs); out_nngp may
+ * be NULL.
+ */
+int nko_myrtle_ntk_pairs(const float* x1, const double* q1, const float* x2, const double* q2, int H, int W,
+                         int C, int n_stages, const int* depth, double sw2, double sb2, const int64_t* pairs,
+                         int64_t npairs, double* out_nngp, double* out_ntk, int nthreads) {
+  nko_myrtle m;
+  memset(&m, 0, sizeof m);
+  m.H = H; m.W = W; m.C = C; m.n_stages = n_stages; m.sw2 = sw2; m.sb2 = sb2;
+  if (n_stages <= 0 || n_stages > 8) return -1;
+  for (int s = 0; s < n_stages; ++s) m.depth[s] = depth[s];
+  if (check_myrtle(&m) || npairs < 0) return -1;
+  size_t qlen = qmaps_len(&m), npix = (size_t)H * W, n4 = npix * npix;
+  int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+  {
+    double* xa = (double*)malloc(npix * C * sizeof(double));
+    double* xb = (double*)malloc(npix * C * sizeof(double));
+    double* bufs[5];
+    int ok = xa && xb;
+    for (int k = 0; k < 5; ++k) {
+      bufs[k] = (double*)malloc(n4 * sizeof(double));
+      ok = ok && bufs[k];
+    }
+    if (!ok) {
+#pragma omp atomic write
+      err = -4;
+    } else {
+#pragma omp for schedule(dynamic, 1)
+      for (int64_t p = 0; p < npairs; ++p) {
+        int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
+        promote(x1 + (size_t)a * npix * C, xa, npix * C);
+        promote(x2 + (size_t)b * npix * C, xb, npix * C);
+        double kn, kt;
+        myrtle_pair_ntk(&m, xa, xb, q1 + (size_t)a * qlen, q2 + (size_t)b * qlen, bufs, &kn, &kt);
+        if (out_nngp) out_nngp[p] = kn;
+        out_ntk[p] = kt;
+      }
+    }
+    free(xa); free(xb);
+    for (int k = 0; k < 5; ++k) free(bufs[k]);
+  }
+  return err;
+}
+
+/* E[relu' relu'] itself, exposed for the quadrature pin. */
+double nko_relu_dot(double s, double q1, double q2) { return relu_dot(s, q1, q2); }
 
 size_t nko_myrtle_qmaps_len(int H, int W, int n_stages, const int* depth) {
   nko_myrtle m;
