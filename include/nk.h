@@ -54,7 +54,14 @@ enum {
 };
 
 /* Operation ids for nk_workspace_size. */
-enum { NK_OP_FC = 0, NK_OP_MYRTLE = 1, NK_OP_MYRTLE_BWD = 2, NK_OP_KRR = 3, NK_OP_MYRTLE_BATCHED = 4 };
+enum {
+  NK_OP_FC = 0,
+  NK_OP_MYRTLE = 1,
+  NK_OP_MYRTLE_BWD = 2,
+  NK_OP_KRR = 3,
+  NK_OP_MYRTLE_BATCHED = 4,
+  NK_OP_MYRTLE_NTK = 5
+};
 
 /*
  * Myrtle network (App. A, Myrtle listing): n_stages stages; stage s runs
@@ -122,6 +129,21 @@ int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const n
  */
 int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K,
                    int64_t ldk, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Myrtle neural tangent kernel block, the kernel of the paper's large-scale
+ * runs (Sec. "Approaches to large-scale kernel methods": the 10-layer Myrtle
+ * NTK), for the network of nk_myrtle_nngp in the parameterisation where each
+ * layer scales N(0, 1) weights by sqrt(sigma_w2 / fan_in) and N(0, 1) biases
+ * by sqrt(sigma_b2): K_ntk[a, b] = sum over all parameters of the products of
+ * the derivatives of the network output at x1[a] and x2[b], in the
+ * infinite-width limit.  The same pass yields the NNGP, written to K_nngp if
+ * it is not NULL (both blocks share ldk).  Same shapes, symmetric-block rule,
+ * workspace convention (op NK_OP_MYRTLE_NTK) and stream semantics as
+ * nk_myrtle_nngp.
+ */
+int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K_ntk,
+                  float* K_nngp, int64_t ldk, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of nk_myrtle_nngp: given the cotangent dK (n1 x n2, leading

@@ -23,6 +23,7 @@ NK_OP_MYRTLE = 1
 NK_OP_MYRTLE_BWD = 2
 NK_OP_KRR = 3
 NK_OP_MYRTLE_BATCHED = 4
+NK_OP_MYRTLE_NTK = 5
 
 
 class MyrtleCfg(ctypes.Structure):
@@ -78,6 +79,8 @@ def lib():
     L.nk_fc_nngp.restype = ci
     L.nk_myrtle_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, i64, P, sz, P]
     L.nk_myrtle_nngp.restype = ci
+    L.nk_myrtle_ntk.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, P, i64, P, sz, P]
+    L.nk_myrtle_ntk.restype = ci
     L.nk_myrtle_nngp_backward.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, i64, P, P, P, P, sz, P]
     L.nk_myrtle_nngp_backward.restype = ci
     L.nk_krr_predict.argtypes = [P, i64, P, i64, P, i64, ctypes.c_double, P, P, sz, P]

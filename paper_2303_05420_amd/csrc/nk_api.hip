@@ -464,6 +464,55 @@ void drop_graph(GraphEntry& e) {
   e.graph = nullptr;
 }
 
+
+// ---- neural tangent kernel -------------------------------------------------
+
+// kappa of layer l of stage s (the scale of the next linear step on that
+// ReLU output), as the variance tables fold it into beta: sigma_w2 / 9 inside
+// a stage, times 1/16 per pool before the next layer, sigma_w2 / n^4 before
+// the readout.
+double layer_kappa(const NetDesc& net, int s, int l) {
+  const double c = (double)net.sw2 / 9.0;
+  if (l + 1 < net.depth[s]) return c;
+  int s2 = s + 1;
+  double f = 1.0 / 16.0;
+  while (s2 < net.S && net.depth[s2] == 0) {
+    f /= 16.0;
+    ++s2;
+  }
+  const double n = (double)(net.hw >> s);
+  return s2 < net.S ? c * f : (double)net.sw2 / (n * n * n * n);
+}
+
+MyrtlePlan plan_ntk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, int64_t chunk) {
+  // the NNGP plan with every chunk buffer twice (the carried NNGP and tangent tiles)
+  MyrtlePlan p;
+  Bump b;
+  const size_t tl = (size_t)nk::table_len(net) * sizeof(float2);
+  p.tab1 = b.take(tl * n1);
+  p.tab2 = sym ? p.tab1 : b.take(tl * n2);
+  const int64_t pb = std::min<int64_t>(std::max(n1, n2), kPrepBlocks);
+  p.scratch = b.take((size_t)nk::prep_scratch_doubles(net) * sizeof(double) * pb);
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    p.buf[s] = b.take(2 * n * n * n * n * sizeof(float) * chunk);
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
+int64_t max_chunk_ntk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size_t ws_bytes, int64_t npairs) {
+  const size_t fixed = plan_ntk(net, n1, n2, sym, 0).total;
+  size_t per = 0;
+  for (int s = 1; s < net.S; ++s) {
+    const size_t n = (size_t)(net.hw >> s);
+    per += 2 * n * n * n * n * sizeof(float);
+  }
+  if (ws_bytes < fixed + 256 * NK_MAX_STAGES) return 0;
+  if (per == 0) return npairs;
+  return std::min((int64_t)((ws_bytes - fixed - 256 * NK_MAX_STAGES) / per), npairs);
+}
+
 // Myrtle Gram block through the stage kernels (tables already prepared).
 int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym,
                      const float2* tab1, const float2* tab2, float* K, int64_t ldk, float* const* bufs,
@@ -580,6 +629,12 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
     }
     case NK_OP_KRR:
       return krr_plan(n1, n2).total;
+    case NK_OP_MYRTLE_NTK: {
+      NetDesc net;
+      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
+      const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
+      return plan_ntk(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 256 * NK_MAX_STAGES;
+    }
     case NK_OP_MYRTLE_BATCHED: {
       NetDesc net;
       if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
@@ -649,6 +704,69 @@ int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, con
   for (int st = 1; st < net.S; ++st) bufs[st] = at<float>(ws, p.buf[st]);
   rc = run_myrtle_pairs(net, x1, n1, x2, n2, sym, tab1, tab2, K, ldk, bufs, chunk, s);
   if (rc) return rc;
+  return ok();
+}
+
+int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K_ntk,
+                  float* K_nngp, int64_t ldk, void* ws, size_t ws_bytes, void* stream) {
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!x1 || !x2 || !K_ntk) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0) return fail(NK_EINVAL, "n1 and n2 must be positive");
+  if (ldk < n2) return fail(NK_EINVAL, "ldk < n2");
+  if (!ws) return fail(NK_EINVAL, "workspace is NULL");
+  for (int st = 0; st < net.S; ++st)
+    if (nk::stage_ntk_lds_bytes(net.hw >> st, net.depth[st], st + 1 < net.S, st == 0) > kLdsDynamicMax)
+      return fail(NK_EUNSUPPORTED, "tangent-kernel stage %d needs more than 160 KiB of LDS", st);
+  const bool sym = (x1 == x2) && (n1 == n2);
+  const int64_t npairs = nk::pair_count(n1, n2, sym);
+  const int64_t chunk = max_chunk_ntk(net, n1, n2, sym, ws_bytes, npairs);
+  if (chunk < 1)
+    return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
+                plan_ntk(net, n1, n2, sym, 1).total + 256 * NK_MAX_STAGES);
+  const MyrtlePlan p = plan_ntk(net, n1, n2, sym, chunk);
+  hipStream_t s = (hipStream_t)stream;
+  float2* tab1 = at<float2>(ws, p.tab1);
+  float2* tab2 = at<float2>(ws, p.tab2);
+  double* scratch = at<double>(ws, p.scratch);
+  {
+    ProfScope ps("myrtle_prepare", s);
+    if (nk::launch_prepare(x1, n1, net, tab1, scratch, kPrepBlocks, s)) return hip_fail("prepare kernel");
+    if (!sym && nk::launch_prepare(x2, n2, net, tab2, scratch, kPrepBlocks, s)) return hip_fail("prepare kernel");
+  }
+  float* bufA[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  float* bufC[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  for (int st = 1; st < net.S; ++st) {
+    const size_t n = (size_t)(net.hw >> st);
+    bufA[st] = at<float>(ws, p.buf[st]);
+    bufC[st] = bufA[st] + n * n * n * n * (size_t)chunk;
+  }
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, npairs - p0);
+    for (int st = 0; st < net.S; ++st) {
+      nk::StageArgs a;
+      memset(&a, 0, sizeof a);
+      a.n1 = n1; a.n2 = n2; a.sym = sym ? 1 : 0; a.T = kPairTile; a.p0 = p0; a.np = np;
+      a.x1 = x1; a.x2 = x2; a.tab1 = tab1; a.tab2 = tab2;
+      a.tablen = nk::table_len(net); a.taboff = nk::table_off(net, st);
+      a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      const bool pool = st + 1 < net.S;
+      a.in = st > 0 ? bufA[st] : nullptr;
+      a.in2 = st > 0 ? bufC[st] : nullptr;
+      a.out = pool ? bufA[st + 1] : nullptr;
+      a.out2 = pool ? bufC[st + 1] : nullptr;
+      a.K = K_nngp;
+      a.K2 = K_ntk;
+      a.ldk = ldk;
+      for (int l = 0; l < net.depth[st]; ++l) a.kh[l] = (float)(0.5 * layer_kappa(net, st, l));
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_ntk_stage%d_n%d", st + 1, net.hw >> st);
+      ProfScope ps(nm, s);
+      if (nk::launch_stage_ntk(net.hw >> st, a, st == 0, pool, net.sb2 != 0.f, s))
+        return hip_fail("tangent-kernel stage kernel");
+    }
+  }
   return ok();
 }
 

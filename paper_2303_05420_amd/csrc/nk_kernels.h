@@ -44,8 +44,14 @@ struct StageArgs {
   float sb2, seed_scale;
   const float* in;  // [np][N][N][N][N]      (stages after the first)
   float* out;       // [np][N/2][N/2][N/2][N/2] (pooling stages)
-  float* K;         // final stage
+  float* K;         // final stage (NULL: not written)
   int64_t ldk;
+  // tangent kernel (NTK launches only): the carried C tiles in and out, the
+  // NTK block (same ldk), kappa / 2 of each layer of the stage
+  const float* in2;
+  float* out2;
+  float* K2;
+  float kh[NK_MAX_DEPTH];
 };
 
 struct StageBwdArgs {
@@ -101,6 +107,8 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
                    int64_t max_blocks, hipStream_t stream);
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
+size_t stage_ntk_lds_bytes(int N, int D, bool pool, bool seed);
+int launch_stage_ntk(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
 int prime_stage(int N, int D, bool seed, bool pool, bool bias);  // kernel attributes, no launch
 int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t stream);
 int stage_occupancy(int N, int D, bool seed, bool pool, bool bias);  // resident workgroups per CU

@@ -6,19 +6,31 @@
 
 namespace nk {
 
-template <int N>
+// Workgroup shape of the forward stage kernel.  A segment of N lanes owns
+// CPS tile columns; the 32x32 tangent kernel (two tiles per column plus
+// their pooling rows) takes two columns per segment on half the lanes, so
+// that each wave has twice the registers.
+template <int N, bool NTK = false>
 struct KCfg {
-  static constexpr int THREADS = (N * N > 256) ? N * N : 256;
-  static constexpr int PPWG = THREADS / (N * N);
+  static constexpr int CPS = (NTK && N == 32) ? 2 : 1;  // tile columns per segment
+  static constexpr int LPP = N * N / CPS;                // lanes per pair
+  static constexpr int THREADS = LPP > 256 ? LPP : 256;
+  static constexpr int PPWG = THREADS / LPP;
 };
 
-// LDS per pair: [tables x1: D N^2 float2][tables x2, rows twice: 2 D N^2 float2]
-// [pooling row / readout partials][images as float4 (seeding stage only):
-// x1, then x2 with its rows twice]
+// LDS bytes of one carried quantity's pooling row (or readout partials).
 template <int N>
-__host__ __device__ inline size_t slot_lds_bytes(int D, bool pool, bool seed) {
+__host__ __device__ constexpr size_t red_bytes_q(bool pool) {
+  return pool ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
+}
+
+// LDS per pair: [tables x1: D N^2 float2][tables x2, rows twice: 2 D N^2 float2]
+// [pooling row / readout partials, per carried quantity][images as float4
+// (seeding stage only): x1, then x2 with its rows twice]
+template <int N>
+__host__ __device__ inline size_t slot_lds_bytes(int D, bool pool, bool seed, bool ntk = false) {
   size_t t = (size_t)D * N * N * 8 + (size_t)D * 2 * N * N * 8 + (seed ? (size_t)3 * N * N * 16 : 0);
-  size_t r = pool ? (size_t)N * N * N / 8 * 4 : (size_t)N * N * 8;
+  size_t r = red_bytes_q<N>(pool) * (ntk ? 2 : 1);
   if (r < 16) r = 16;
   return (t + r + 15) & ~(size_t)15;
 }
@@ -66,6 +78,69 @@ __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restri
     A[r] = (a.y * b.y) * J;
     hm = h0;
     h0 = hp;
+  }
+}
+
+// One layer of the tangent kernel on the tile pair (A, C): A as tile_layer
+// (kappa F), C = kappa (F + Fdot T) with T = box(C) + sigma_b2, or T = S on
+// the network's first layer (SIGNED), whose C input is not read.
+// kh = kappa / 2 of this layer; kappa Fdot = kh (1 - acos(rho) / pi), and
+// kh acos(|rho|) / pi for rho < 0.  acos has an infinite slope at rho = 1, so
+// the rounding of rho (about 1e-7) would move Fdot by about 1e-4 where rho
+// is 1 exactly: on the displacement-0 tile of a pair of identical images
+// (i = j) the caller passes umax = 0, which pins u = 1 - rho to 0 there
+// (umax = 1 elsewhere: the plain clamp).
+template <int N, bool SIGNED, bool BIAS>
+__device__ __forceinline__ void tile_layer_ntk(float (&A)[N], float (&C)[N], const float2* __restrict__ c1,
+                                               const float2* __restrict__ c2, int seam, float mL, float mR,
+                                               float sb2, float kh, float umax) {
+  float hm = 0.f;
+  float h0 = hsum3(A[0], mL, mR);
+  float gm = 0.f;
+  float g0 = SIGNED ? 0.f : hsum3(C[0], mL, mR);
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    float hp = 0.f, gp = 0.f;
+    if (r + 1 < N) {
+      hp = hsum3(A[r + 1], mL, mR);
+      if (!SIGNED) gp = hsum3(C[r + 1], mL, mR);
+    }
+    const float mu = uniform_mask(r == seam), md = uniform_mask(r + 1 == seam);
+    float v = h0;
+    if (r > 0) v = __builtin_fmaf(mu, hm, v);
+    if (r + 1 < N) v = __builtin_fmaf(md, hp, v);
+    if (BIAS) v += sb2;
+    float vt = v;
+    if (!SIGNED) {
+      vt = g0;
+      if (r > 0) vt = __builtin_fmaf(mu, gm, vt);
+      if (r + 1 < N) vt = __builtin_fmaf(md, gp, vt);
+      if (BIAS) vt += sb2;
+    }
+    const float2 a = c1[r * N];
+    const float2 b = c2[r * N];
+    const float rr = a.x * b.x;
+    float J, th;
+    if (SIGNED) {
+      const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-__builtin_fabsf(v), rr, 1.0f), 0.0f, umax);
+      const float cc = __builtin_amdgcn_fmed3f(__builtin_fmaf(v, rr, 1.0f), 0.0f, 1.0f);
+      const float sq = __builtin_amdgcn_sqrtf(u);
+      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), cc);
+      th = sq * acos_g(u) * 0.31830988618379067f;
+    } else {
+      const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-v, rr, 1.0f), 0.0f, umax);
+      const float sq = __builtin_amdgcn_sqrtf(u);
+      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), 1.0f);
+      th = sq * acos_g(u) * 0.31830988618379067f;
+    }
+    const float kfd = (SIGNED && v < 0.f) ? kh * th : __builtin_fmaf(-th, kh, kh);
+    const float an = (a.y * b.y) * J;
+    A[r] = an;
+    C[r] = __builtin_fmaf(kfd, vt, an);
+    hm = h0;
+    h0 = hp;
+    gm = g0;
+    g0 = gp;
   }
 }
 

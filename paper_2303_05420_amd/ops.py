@@ -76,6 +76,35 @@ def myrtle_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: Sequence[int],
     return out[:, :n2] if out.shape[1] != n2 else out
 
 
+def myrtle_ntk(x1: torch.Tensor, x2: torch.Tensor | None, depth: Sequence[int], sigma_w2: float = 2.0,
+               sigma_b2: float = 0.0, with_nngp: bool = False, ws: torch.Tensor | None = None):
+    """Myrtle neural tangent kernel block Theta[a, b] (x2=None: x1 x x1).  With
+    with_nngp=True returns (Theta, K) where K is the NNGP of the same pass."""
+    _check_images(x1, "x1")
+    sym = x2 is None
+    if sym:
+        x2 = x1
+    else:
+        _check_images(x2, "x2")
+    if x2.shape[1:] != x1.shape[1:]:
+        raise ValueError("x1 and x2 image shapes differ")
+    n1, h, w, c = x1.shape
+    n2 = x2.shape[0]
+    cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
+    th = torch.empty((n1, n2), dtype=torch.float32, device=x1.device)
+    k = torch.empty((n1, n2), dtype=torch.float32, device=x1.device) if with_nngp else None
+    if ws is None:
+        need = workspace_size(_lib.NK_OP_MYRTLE_NTK, cfg, n1, n2)
+        if need == 0:
+            _lib.check(_lib.lib().nk_myrtle_ntk(None, 0, None, 0, ctypes.byref(cfg), None, None, 0, None, 0, None))
+        ws = workspace(need, x1.device)
+    rc = _lib.lib().nk_myrtle_ntk(x1.data_ptr(), n1, x2.data_ptr(), n2, ctypes.byref(cfg), th.data_ptr(),
+                                  None if k is None else k.data_ptr(), n2, ws.data_ptr(), ws.numel(),
+                                  _stream(x1.device))
+    _lib.check(rc)
+    return (th, k) if with_nngp else th
+
+
 def fc_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 3, sigma_w2: float = 2.0,
             sigma_b2: float = 0.01, out: torch.Tensor | None = None) -> torch.Tensor:
     """FC NNGP block on the flattened inputs."""

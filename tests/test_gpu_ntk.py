@@ -1,0 +1,101 @@
+"""GPU parity of the Myrtle neural tangent kernel (nk_myrtle_ntk) against
+the FP64 oracle: max |Theta_gpu - Theta_oracle| / sqrt(Theta(x,x) Theta(x',x'))
+<= 2e-5, and the NNGP of the same pass against the NNGP oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_05420_amd import ops
+    return ops
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _check(nk, x1, x2, depth, sb2=0.0, sw2=2.0):
+    net = oracle.Myrtle(depth, sw2, sb2)
+    _say(f"ntk block {x1.shape} x {None if x2 is None else x2.shape} depth={depth} sb2={sb2}")
+    th, k = nk.myrtle_ntk(_gpu(x1), None if x2 is None else _gpu(x2), depth, sw2, sb2, with_nngp=True)
+    th = th.cpu().numpy()
+    k = k.cpu().numpy()
+    rn, rt = oracle.myrtle_ntk_gram(x1, x2, net)
+    # self values for the normalisation
+    d1n, d1t = oracle.myrtle_ntk_pairs(x1, x1, np.stack([np.arange(len(x1))] * 2, 1), net)
+    if x2 is None:
+        d2n, d2t = d1n, d1t
+    else:
+        d2n, d2t = oracle.myrtle_ntk_pairs(x2, x2, np.stack([np.arange(len(x2))] * 2, 1), net)
+    et = float(np.max(np.abs(th - rt) / np.sqrt(np.outer(d1t, d2t))))
+    en = float(np.max(np.abs(k - rn) / np.sqrt(np.outer(d1n, d2n))))
+    _say(f"  normalised error NTK {et:.3e}  NNGP {en:.3e}")
+    assert et <= TOL and en <= TOL
+    return th, k
+
+
+@pytest.mark.parametrize("n1,n2,hw,depth,sb2", [
+    (13, 9, 8, (2, 1, 1), 0.0),
+    (6, 7, 8, (2, 0, 1), 0.1),
+    (5, 4, 16, (2, 2, 2), 0.0),
+    (3, 2, 4, (1, 1), 0.05),
+    (4, 3, 2, (3,), 0.0),
+])
+def test_ntk_blocks_match_oracle(nk, n1, n2, hw, depth, sb2):
+    x1 = synth.correlated_images(n1, hw, hw, 3, 1.5, 61)
+    x2 = synth.correlated_images(n2, hw, hw, 3, 1.5, 62)
+    _check(nk, x1, x2, depth, sb2)
+
+
+def test_ntk_symmetric_block(nk):
+    x = synth.iid_images(20, 8, 8, 3, 63)
+    th, _ = _check(nk, x, None, (2, 1, 1), 0.02)
+    assert np.array_equal(th, th.T)
+
+
+def test_ntk_nngp_agrees_with_nngp_entry_point(nk):
+    x1 = synth.correlated_images(9, 16, 16, 3, 2.0, 64)
+    x2 = synth.correlated_images(11, 16, 16, 3, 2.0, 65)
+    th, k = nk.myrtle_ntk(_gpu(x1), _gpu(x2), (2, 1, 1), with_nngp=True)
+    k0 = nk.myrtle_nngp(_gpu(x1), _gpu(x2), (2, 1, 1))
+    # same recursion, pooled sums in another order: float32 rounding only
+    err = float((k - k0).abs().max() / k0.abs().max())
+    _say(f"  NNGP of the NTK pass vs the NNGP entry point: {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_ntk_myrtle10_32x32_sampled(nk):
+    w = synth.WORKLOADS["myrtle10_32x32_4096"]
+    n = 48
+    x1 = synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][0])
+    x2 = synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][1])
+    _say("ntk myrtle10 48 x 48 at 32x32 on GPU")
+    th = nk.myrtle_ntk(_gpu(x1), _gpu(x2), w["depth"]).cpu().numpy()
+    rng = np.random.default_rng(66)
+    pairs = np.stack([rng.integers(0, n, 12), rng.integers(0, n, 12)], 1)
+    net = oracle.Myrtle(w["depth"], w["sigma_w2"], w["sigma_b2"])
+    _say("oracle on 12 sampled pairs")
+    _, rt = oracle.myrtle_ntk_pairs(x1, x2, pairs, net)
+    _, d1 = oracle.myrtle_ntk_pairs(x1, x1, np.stack([pairs[:, 0]] * 2, 1), net)
+    _, d2 = oracle.myrtle_ntk_pairs(x2, x2, np.stack([pairs[:, 1]] * 2, 1), net)
+    err = float(np.max(np.abs(th[pairs[:, 0], pairs[:, 1]] - rt) / np.sqrt(d1 * d2)))
+    _say(f"  normalised error {err:.3e}")
+    assert err <= TOL
