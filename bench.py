@@ -42,6 +42,7 @@ def _args():
                    help="also run a plain device copy of this many MiB (counter calibration runs)")
     p.add_argument("--no-fwd-bwd", action="store_true", help="skip the fwd+bwd measurement")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain tile comparison")
+    p.add_argument("--no-ntk", action="store_true", help="skip the Myrtle-10 NTK measurement")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -106,6 +107,31 @@ def _fwd_bwd(torch):
             "loss": loss, "dsigma": [float(v) for v in ds.cpu().tolist()],
             "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
             "stage_kernels_fwd_ms": round(fwd_ms, 3), "stage_kernels_bwd_ms": round(bwd_ms, 3)}
+
+
+def _ntk(torch, n: int = 1024):
+    """Myrtle-10 neural tangent kernel (with its NNGP) on an n x n block of the
+    headline images, timed once after an untimed 64 x 64 pass."""
+    import synth
+    from paper_2303_05420_amd import _lib, ops
+
+    w = synth.WORKLOADS["myrtle10_32x32_4096"]
+    x1 = torch.from_numpy(synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][0])).cuda()
+    x2 = torch.from_numpy(synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][1])).cuda()
+    ops.myrtle_ntk(x1[:64], x2[:64], w["depth"], w["sigma_w2"], w["sigma_b2"])
+    torch.cuda.synchronize()
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    ops.myrtle_ntk(x1, x2, w["depth"], w["sigma_w2"], w["sigma_b2"], with_nngp=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    print(f"ntk: {dt:.2f} s for {n * n} pairs", file=sys.stderr, flush=True)
+    return {"value": round(n * n / dt, 3), "unit": "pairs/s", "pairs": n * n, "ms": round(dt * 1e3, 3),
+            "workload": f"Myrtle-10 NTK and NNGP together, 32x32x3, one {n}x{n} block of the headline images",
+            "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()}}
 
 
 def _batched(torch, full: bool):
@@ -240,6 +266,7 @@ def main():
 
     fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
     batched = None if a.no_batched else _batched(torch, a.batched_full)
+    ntk = None if a.no_ntk else _ntk(torch)
 
     cpu = None
     parity = None
@@ -287,6 +314,7 @@ def main():
         "parity": parity,
         "fwd_bwd": fwd_bwd,
         "batched_tiles": batched,
+        "ntk": ntk,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))
