@@ -20,6 +20,8 @@ Contents
   same recursion, used as the reference for kernel gradients.
 * ``matrix_form`` (submodule) -- joint-covariance-matrix form of the Myrtle
   recursion for tiny images, used to pin the C loop nest.
+* ``solvers`` (submodule) -- the partial pivoted Cholesky preconditioner and
+  preconditioned conjugate gradients in float64 (Sec. 2, iterative solvers).
 """
 from __future__ import annotations
 
