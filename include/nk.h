@@ -60,7 +60,10 @@ enum {
   NK_OP_MYRTLE_BWD = 2,
   NK_OP_KRR = 3,
   NK_OP_MYRTLE_BATCHED = 4,
-  NK_OP_MYRTLE_NTK = 5
+  NK_OP_MYRTLE_NTK = 5,
+  NK_OP_PCG = 6,          /* cfg: nk_pcg_cfg; n1 = n, n2 = c */
+  NK_OP_PIVOTED_CHOL = 7, /* cfg: NULL; n1 = n, n2 = rank */
+  NK_OP_GRAM_MATVEC = 8   /* cfg: NULL; n1 = n, n2 = c */
 };
 
 /*
@@ -243,6 +246,88 @@ typedef struct {
  * for this configuration in this process. */
 int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
                              nk_batched_candidate* chosen);
+
+/*
+ * Partial pivoted Cholesky factor of a symmetric positive semi-definite
+ * Gram matrix, the preconditioner of the paper's conjugate-gradient solver
+ * (Sec. 2, "Iterative solvers"; Sec. 1, related work).  Greedy diagonal
+ * pivoting: with d the diagonal of the current Schur complement (diag K at
+ * the start), step m picks the not-yet-picked index p of largest d (lowest
+ * index on ties), stops if d_p <= 0 or d_p <= pivot_tol * max(diag K), and
+ * otherwise appends column m of L:
+ *   L[p][m] = sqrt(d_p),
+ *   L[i][m] = (K[p][i] - sum_{k<m} L[p][k] L[i][k]) / sqrt(d_p)  (i not picked),
+ *   L[i][m] = 0 at indices picked earlier;  then d_i -= L[i][m]^2.
+ * K: n x n float32 device, row-major, leading dim ldk >= n (read, symmetric;
+ * the row of each pivot is read).  L: n x rank float64 device, COLUMN-major
+ * (column m at L + m n); columns past the rank reached are zero.  piv: rank
+ * int32 device (pivot of each column, -1 past the rank reached).
+ * *rank_used (host, may be NULL): columns produced.  0 <= rank <= min(n,
+ * 8192).  Workspace: nk_workspace_size(NK_OP_PIVOTED_CHOL, NULL, n, rank).
+ * Float64 throughout; synchronises `stream`.
+ */
+int nk_pivoted_cholesky(const float* K, int64_t n, int64_t ldk, int32_t rank, double pivot_tol, double* L,
+                        int32_t* piv, int32_t* rank_used, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Kernel-vector products of the solver: Q = (K + lambda I) P, the one place
+ * the kernel enters conjugate gradients (Sec. 2, "Iterative solvers";
+ * Fig. 1 splits this product over workers).  K: n x n float32 device,
+ * row-major, leading dim ldk >= n, SYMMETRIC (the product reads K by rows
+ * and uses K = K^T); P, Q: n x c float64 device, row-major (leading dim c);
+ * 1 <= c <= 16.  Float64 products and sums, in a fixed order (bitwise
+ * reproducible).  Workspace: nk_workspace_size(NK_OP_GRAM_MATVEC, NULL, n,
+ * c).  Asynchronous on `stream`.
+ */
+int nk_gram_matvec(const float* K, int64_t n, int64_t ldk, const double* P, int64_t c, double lambda, double* Q,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Solver settings of nk_krr_pcg.
+ *   rank      preconditioner rank r >= 0 (0: no preconditioner, plain CG);
+ *             at most min(n, 8192)
+ *   max_iter  iteration cap >= 1
+ *   tol       column j stops once ||r_j|| <= tol ||y_j|| (recursive residual)
+ *   pivot_tol the pivoted Cholesky stops early when the largest residual
+ *             diagonal is <= pivot_tol * max(diag K) (0: only at d <= 0)
+ */
+typedef struct {
+  int32_t rank;
+  int32_t max_iter;
+  double tol;
+  double pivot_tol;
+} nk_pcg_cfg;
+
+/* Outcome of nk_krr_pcg. */
+typedef struct {
+  int32_t rank;       /* preconditioner rank reached */
+  int32_t iterations; /* largest iteration count over the columns */
+  double lambda;      /* ridge used */
+} nk_pcg_stats;
+
+/*
+ * Kernel ridge regression by preconditioned conjugate gradients in float64
+ * (Sec. 2, "Iterative solvers", with the partial pivoted Cholesky
+ * preconditioner; the paper solves in high precision, Sec. 1): solves
+ * (K + lambda I) X = Y column by column, lambda = ridge, or ridge *
+ * mean(diag K) when ridge_is_relative != 0 (lambda must come out > 0).
+ * Preconditioner Ph = L L^T + lambda I with L = nk_pivoted_cholesky(K,
+ * cfg->rank), applied by the Woodbury identity.  Each column runs the
+ * textbook PCG recursion from X = 0 and stops (its X frozen) after the
+ * first update that brings ||r|| <= tol ||y||; a zero column of Y gives
+ * X = 0 after 0 iterations.
+ * K: n x n float32 device, row-major, ldk >= n, symmetric.  Y: n x c
+ * float64 device, row-major (leading dim c).  X: n x c float64 device
+ * output.  iters (c int32) and relres (c doubles, ||r||/||y|| at the
+ * column's last update) are host arrays, may be NULL; stats (host) may be
+ * NULL.  Columns are solved in groups of 16.  Workspace:
+ * nk_workspace_size(NK_OP_PCG, cfg, n, c).  Synchronises `stream` (it reads
+ * lambda, the rank reached and the convergence flags on the host).
+ * NK_ENOTPD if lambda I + L^T L cannot be factored.
+ */
+int nk_krr_pcg(const float* K, int64_t n, int64_t ldk, const double* Y, int64_t c, double ridge,
+               int ridge_is_relative, const nk_pcg_cfg* cfg, double* X, int32_t* iters, double* relres,
+               nk_pcg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing (tracing).  After nk_profile_enable(1), every launch of the

@@ -24,6 +24,9 @@ NK_OP_MYRTLE_BWD = 2
 NK_OP_KRR = 3
 NK_OP_MYRTLE_BATCHED = 4
 NK_OP_MYRTLE_NTK = 5
+NK_OP_PCG = 6
+NK_OP_PIVOTED_CHOL = 7
+NK_OP_GRAM_MATVEC = 8
 
 
 class MyrtleCfg(ctypes.Structure):
@@ -45,6 +48,15 @@ class Tile(ctypes.Structure):
 class BatchedCandidate(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int64), ("pair_tile", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("us_per_pair", ctypes.c_double)]
+
+
+class PcgCfg(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("pivot_tol", ctypes.c_double)]
+
+
+class PcgStats(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("iterations", ctypes.c_int32), ("lambda_", ctypes.c_double)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -95,6 +107,14 @@ def lib():
     L.nk_myrtle_batched_tuning.argtypes = [ctypes.POINTER(MyrtleCfg), ctypes.POINTER(BatchedCandidate), ci,
                                            ctypes.POINTER(BatchedCandidate)]
     L.nk_myrtle_batched_tuning.restype = ci
+    dbl = ctypes.c_double
+    L.nk_pivoted_cholesky.argtypes = [P, i64, i64, i32, dbl, P, P, ctypes.POINTER(i32), P, sz, P]
+    L.nk_pivoted_cholesky.restype = ci
+    L.nk_gram_matvec.argtypes = [P, i64, i64, P, i64, dbl, P, P, sz, P]
+    L.nk_gram_matvec.restype = ci
+    L.nk_krr_pcg.argtypes = [P, i64, i64, P, i64, dbl, ci, ctypes.POINTER(PcgCfg), P, P, P,
+                             ctypes.POINTER(PcgStats), P, sz, P]
+    L.nk_krr_pcg.restype = ci
     L.nk_profile_enable.argtypes = [ci]
     L.nk_profile_enable.restype = ci
     L.nk_profile_read.argtypes = [ctypes.POINTER(ProfileEntry), ci, ci]

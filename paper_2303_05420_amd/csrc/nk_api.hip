@@ -553,6 +553,81 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
   return NK_OK;
 }
 
+
+// ---- kernel regression by preconditioned conjugate gradients --------------
+
+constexpr int kPcgMaxRank = 8192;  // LDS of a pivot step holds one row of L
+constexpr int kPcgGroup = 16;      // right-hand sides per CG pass
+
+// Row splits of L^T v: about 1024 single-wave workgroups, >= 64 rows each.
+int pc_lt_splits(int64_t n, int r) {
+  if (r <= 0) return 1;
+  const int64_t g = (r + 63) / 64;
+  int64_t S = (1024 + g - 1) / g;
+  S = std::min<int64_t>(S, (n + 63) / 64);
+  return (int)std::max<int64_t>(S, 1);
+}
+
+struct PcgPlan {
+  size_t d, pv, pi, dpiv, mean, piv, L, Lr, M, info, W, wpart, R, X, Z, P, Q, kpart, part1, part2, st;
+  int lt_splits;
+  size_t total;
+};
+
+// what: 0 = pivoted Cholesky only, 1 = full solver, 2 = product only
+PcgPlan pcg_plan(int64_t n, int r, int what) {
+  PcgPlan p{};
+  Bump b;
+  const int64_t nb = (n + 255) / 256;
+  const size_t G = kPcgGroup;
+  if (what != 2) {
+    p.d = b.take(sizeof(double) * n);
+    p.pv = b.take(sizeof(double) * 2 * nb);
+    p.pi = b.take(sizeof(int) * 2 * nb);
+    p.dpiv = b.take(sizeof(double) * std::max(r, 1));
+  }
+  if (what == 1) {
+    p.mean = b.take(sizeof(double) * 2);
+    p.piv = b.take(sizeof(int) * std::max(r, 1));
+    p.L = b.take(sizeof(double) * (size_t)n * r);
+    p.Lr = b.take(sizeof(double) * (size_t)n * r);
+    p.M = b.take(sizeof(double) * (size_t)r * r);
+    p.info = b.take(sizeof(int) * 4);
+    p.lt_splits = pc_lt_splits(n, r);
+    p.W = b.take(sizeof(double) * std::max(r, 1) * G);
+    p.wpart = b.take(sizeof(double) * (size_t)p.lt_splits * std::max(r, 1) * G);
+    p.R = b.take(sizeof(double) * n * G);
+    p.X = b.take(sizeof(double) * n * G);
+    p.Z = b.take(sizeof(double) * n * G);
+    p.P = b.take(sizeof(double) * n * G);
+    p.Q = b.take(sizeof(double) * n * G);
+    p.part2 = b.take(sizeof(double) * nb * G);
+    p.st = b.take(sizeof(double) * 6 * G);
+  }
+  if (what != 0) {
+    p.kpart = b.take(sizeof(double) * (size_t)nk::kmv_splits(n) * n * G);
+    p.part1 = b.take(sizeof(double) * nb * G);
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
+// Event bracket of the library's timing records, for one launch inside a launcher.
+struct ScopeHook : nk::ProfHook {
+  const char* name;
+  ProfScope* cur = nullptr;
+  explicit ScopeHook(const char* nm) : name(nm) {}
+  void begin(hipStream_t s) override {
+    delete cur;
+    cur = new ProfScope(name, s);
+  }
+  void end(hipStream_t) override {
+    delete cur;
+    cur = nullptr;
+  }
+  ~ScopeHook() override { delete cur; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -640,6 +715,17 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
       if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
       return plan_batched(net, n1, std::max<int64_t>(n2, 1), kDefaultChunk).total + 256 * NK_MAX_STAGES;
     }
+    case NK_OP_PCG: {
+      const nk_pcg_cfg* c = static_cast<const nk_pcg_cfg*>(cfg);
+      if (!c || n1 <= 0 || c->rank < 0) return 0;
+      return pcg_plan(n1, (int)std::min<int64_t>(c->rank, n1), 1).total;
+    }
+    case NK_OP_PIVOTED_CHOL:
+      if (n1 <= 0) return 0;
+      return pcg_plan(n1, (int)std::min<int64_t>(n2, n1), 0).total;
+    case NK_OP_GRAM_MATVEC:
+      if (n1 <= 0) return 0;
+      return pcg_plan(n1, 0, 2).total;
     default:
       return 0;
   }
@@ -928,6 +1014,167 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
   if (hipStreamSynchronize(s) != hipSuccess) return hip_fail("krr sync");
   if (lambda_used) *lambda_used = ridge_is_relative ? ridge * h_mean : ridge;
   if (h_info) return fail(NK_ENOTPD, "K_ss + lambda I is not positive definite");
+  return ok();
+}
+
+
+int nk_pivoted_cholesky(const float* K, int64_t n, int64_t ldk, int32_t rank, double pivot_tol, double* L,
+                        int32_t* piv, int32_t* rank_used, void* ws, size_t ws_bytes, void* stream) {
+  if (!K || (rank > 0 && (!L || !piv))) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || ldk < n) return fail(NK_EINVAL, "need n > 0 and ldk >= n");
+  if (rank < 0 || rank > n) return fail(NK_EINVAL, "need 0 <= rank <= n");
+  if (rank > kPcgMaxRank) return fail(NK_EUNSUPPORTED, "rank > %d", kPcgMaxRank);
+  if (!(pivot_tol >= 0.0)) return fail(NK_EINVAL, "pivot_tol must be >= 0");
+  if (rank_used) *rank_used = 0;
+  if (rank == 0) return ok();
+  const PcgPlan pp = pcg_plan(n, rank, 0);
+  if (!ws || ws_bytes < pp.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", pp.total);
+  hipStream_t s = (hipStream_t)stream;
+  {
+    ProfScope ps("pivoted_cholesky", s);
+    if (nk::launch_pchol(K, n, ldk, rank, pivot_tol, L, piv, at<double>(ws, pp.d), at<double>(ws, pp.pv),
+                         at<int>(ws, pp.pi), at<double>(ws, pp.dpiv), s))
+      return hip_fail("pivoted cholesky");
+  }
+  std::vector<int32_t> hp(rank);
+  if (hipMemcpyAsync(hp.data(), piv, sizeof(int32_t) * rank, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return hip_fail("pivoted cholesky");
+  int32_t r = 0;
+  while (r < rank && hp[r] >= 0) ++r;
+  if (rank_used) *rank_used = r;
+  return ok();
+}
+
+int nk_gram_matvec(const float* K, int64_t n, int64_t ldk, const double* P, int64_t c, double lambda, double* Q,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (!K || !P || !Q) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || ldk < n) return fail(NK_EINVAL, "need n > 0 and ldk >= n");
+  if (c < 1 || c > kPcgGroup) return fail(NK_EUNSUPPORTED, "need 1 <= c <= %d", kPcgGroup);
+  const PcgPlan pp = pcg_plan(n, 0, 2);
+  if (!ws || ws_bytes < pp.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", pp.total);
+  hipStream_t s = (hipStream_t)stream;
+  ScopeHook hook("gram_matvec");
+  if (nk::launch_kmv(K, n, ldk, P, (int)c, lambda, at<double>(ws, pp.kpart), Q, at<double>(ws, pp.part1), s,
+                     &hook))
+    return hip_fail("gram matvec");
+  return ok();
+}
+
+int nk_krr_pcg(const float* K, int64_t n, int64_t ldk, const double* Y, int64_t c, double ridge,
+               int ridge_is_relative, const nk_pcg_cfg* cfg, double* X, int32_t* iters, double* relres,
+               nk_pcg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!K || !Y || !X || !cfg) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || ldk < n || c <= 0) return fail(NK_EINVAL, "need n > 0, ldk >= n and c > 0");
+  if (cfg->rank < 0 || cfg->max_iter < 1 || !(cfg->tol >= 0.0) || !(cfg->pivot_tol >= 0.0) || !(ridge >= 0.0))
+    return fail(NK_EINVAL, "need rank >= 0, max_iter >= 1, tol >= 0, pivot_tol >= 0, ridge >= 0");
+  const int rank = (int)std::min<int64_t>(cfg->rank, n);
+  if (rank > kPcgMaxRank) return fail(NK_EUNSUPPORTED, "rank > %d", kPcgMaxRank);
+  const PcgPlan pp = pcg_plan(n, rank, 1);
+  if (!ws || ws_bytes < pp.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", pp.total);
+  hipStream_t s = (hipStream_t)stream;
+
+  double lam = ridge;
+  if (ridge_is_relative) {
+    double mean = 0.0;
+    if (nk::launch_diag_mean(K, n, ldk, at<double>(ws, pp.mean), s) ||
+        hipMemcpyAsync(&mean, at<double>(ws, pp.mean), sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return hip_fail("pcg ridge");
+    lam = ridge * mean;
+  }
+  if (!(lam > 0.0)) return fail(NK_EINVAL, "lambda must be > 0 (got %g)", lam);
+
+  double* L = at<double>(ws, pp.L);
+  int r = 0;
+  if (rank > 0) {
+    int* piv = at<int>(ws, pp.piv);
+    {
+      ProfScope ps("pivoted_cholesky", s);
+      if (nk::launch_pchol(K, n, ldk, rank, cfg->pivot_tol, L, piv, at<double>(ws, pp.d), at<double>(ws, pp.pv),
+                           at<int>(ws, pp.pi), at<double>(ws, pp.dpiv), s))
+        return hip_fail("pivoted cholesky");
+    }
+    std::vector<int> hp(rank);
+    if (hipMemcpyAsync(hp.data(), piv, sizeof(int) * rank, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return hip_fail("pivoted cholesky");
+    while (r < rank && hp[r] >= 0) ++r;
+  }
+  if (r > 0) {
+    int info = 0;
+    {
+      ProfScope ps("pcg_precond_setup", s);
+      if (nk::launch_pc_setup(L, n, r, lam, at<double>(ws, pp.Lr), at<double>(ws, pp.M), at<int>(ws, pp.info), s))
+        return hip_fail("preconditioner set-up");
+    }
+    if (hipMemcpyAsync(&info, at<int>(ws, pp.info), sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return hip_fail("preconditioner set-up");
+    if (info) return fail(NK_ENOTPD, "lambda I + L^T L is not positive definite");
+  }
+
+  nk::PcgArgs a{};
+  a.K = K;
+  a.n = n;
+  a.ldk = ldk;
+  a.Y = Y;
+  a.ldy = c;
+  a.Xout = X;
+  a.ldx = c;
+  a.lam = lam;
+  a.tol = cfg->tol;
+  a.max_iter = cfg->max_iter;
+  a.check_every = n >= 8192 ? 1 : 4;
+  a.r = r;
+  a.U = L;  // L R^{-T}, formed in place by the set-up
+  a.Ur = at<double>(ws, pp.Lr);
+  a.W = at<double>(ws, pp.W);
+  a.wpart = at<double>(ws, pp.wpart);
+  a.lt_splits = pp.lt_splits;
+  a.R = at<double>(ws, pp.R);
+  a.X = at<double>(ws, pp.X);
+  a.Z = at<double>(ws, pp.Z);
+  a.P = at<double>(ws, pp.P);
+  a.Q = at<double>(ws, pp.Q);
+  a.kpart = at<double>(ws, pp.kpart);
+  a.part1 = at<double>(ws, pp.part1);
+  a.part2 = at<double>(ws, pp.part2);
+  double* st = at<double>(ws, pp.st);
+  a.gamma = st;
+  a.beta = st + kPcgGroup;
+  a.ynorm = st + 2 * kPcgGroup;
+  a.relres = st + 3 * kPcgGroup;
+  a.active = reinterpret_cast<int*>(st + 4 * kPcgGroup);
+  a.iters = reinterpret_cast<int*>(st + 5 * kPcgGroup);
+  ScopeHook hook("pcg_matvec");
+  a.hook = &hook;
+  int max_it = 0;
+  for (int64_t c0 = 0; c0 < c; c0 += kPcgGroup) {
+    const int C = (int)std::min<int64_t>(kPcgGroup, c - c0);
+    int rc;
+    {
+      ProfScope ps("pcg_solve", s);
+      rc = nk::launch_pcg_group(a, c0, C, s);
+    }
+    if (rc) return hip_fail("pcg");
+    int hit[kPcgGroup];
+    double hrel[kPcgGroup];
+    if (hipMemcpyAsync(hit, a.iters, sizeof(int) * C, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hrel, a.relres, sizeof(double) * C, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return hip_fail("pcg");
+    for (int j = 0; j < C; ++j) {
+      if (iters) iters[c0 + j] = hit[j];
+      if (relres) relres[c0 + j] = hrel[j];
+      max_it = std::max(max_it, hit[j]);
+    }
+  }
+  if (stats) {
+    stats->rank = r;
+    stats->iterations = max_it;
+    stats->lambda = lam;
+  }
   return ok();
 }
 

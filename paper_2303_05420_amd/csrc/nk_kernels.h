@@ -136,4 +136,46 @@ int launch_krr_outer(const double* U, int64_t rows, const double* V, int64_t col
 int launch_krr_matmul(const float* K, int64_t m, int64_t n, int64_t ld, const double* X, int64_t c, float* out,
                       hipStream_t s);
 
+// Event bracket around one launch (the host API times the product that
+// dominates a conjugate-gradient iteration through it).
+struct ProfHook {
+  virtual void begin(hipStream_t s) = 0;
+  virtual void end(hipStream_t s) = 0;
+  virtual ~ProfHook() {}
+};
+
+// One preconditioned conjugate-gradient solve (pcg.hip).  All arrays are
+// device memory; n x C blocks are row-major with leading dim C.
+struct PcgArgs {
+  const float* K;
+  int64_t n, ldk;
+  const double* Y;  // n x ldy, columns c0 .. c0 + C of this group
+  int64_t ldy;
+  double* Xout;     // n x ldx
+  int64_t ldx;
+  double lam, tol;
+  int max_iter, check_every;
+  int r;                 // preconditioner rank (0: Ph = lam I)
+  const double* U;       // n x r, column major: L R^{-T}, R R^T = lam I + L^T L
+  const double* Ur;      // the same, row major
+  double* W;             // r x 16
+  double* wpart;         // lt_splits x r x 16
+  int lt_splits;
+  double *R, *X, *Z, *P, *Q;  // n x 16
+  double* kpart;              // kmv_splits(n) x n x 16
+  double *part1, *part2;      // ceil(n / 256) x 16
+  double *gamma, *beta, *ynorm, *relres;  // 16 each
+  int *active, *iters;                    // 16 each
+  ProfHook* hook;
+};
+
+int launch_pchol(const float* K, int64_t n, int64_t ldk, int rank, double pivot_tol, double* L, int* piv,
+                 double* d, double* pv, int* pi, double* dpiv, hipStream_t s);
+int launch_pc_setup(double* LU, int64_t n, int r, double lam, double* Ur, double* M, int* info, hipStream_t s);
+int launch_pcg_group(const PcgArgs& a, int64_t c0, int C, hipStream_t s);
+int kmv_splits(int64_t n);
+int launch_kmv(const float* K, int64_t n, int64_t ldk, const double* P, int C, double lam, double* part, double* Q,
+               double* pq_part, hipStream_t s, ProfHook* hook);
+int launch_diag_mean(const float* K, int64_t n, int64_t ldk, double* out, hipStream_t s);
+
 }  // namespace nk

@@ -1,0 +1,713 @@
+// Kernel regression by preconditioned conjugate gradients in float64
+// (Sec. 2, "Iterative solvers": CG with the partial pivoted Cholesky
+// preconditioner; Sec. 1, related work: the preconditioner's origin and the
+// need for high precision on neural kernels).
+//
+// System (K + lam I) X = Y, K the float32 Gram matrix the kernel entry points
+// write (n x n, leading dim ldk, row-major, symmetric), Y and X float64
+// (n x c).  Every product and sum runs in float64 on the float32 values of
+// K, so the system solved is exactly double(K) + lam I.
+//
+// Pieces:
+//   * pchol_*: greedy partial pivoted Cholesky K ~ L L^T (L n x r, column
+//     major), one kernel per pivot: every workgroup reduces the previous
+//     step's per-workgroup maxima of the residual diagonal d (largest value,
+//     lowest index on ties), then forms its rows of the new column and
+//     updates d.  Picked indices hold d = -inf.
+//   * The preconditioner Ph = L L^T + lam I is applied with the Woodbury
+//     identity Ph^{-1} v = (v - L M^{-1} L^T v) / lam, M = lam I + L^T L.
+//     With M = R R^T (Cholesky) and U = L R^{-T}, formed once in place of L,
+//     this is (v - U (U^T v)) / lam: two skinny products per application and
+//     an operator that stays symmetric in floating point (an explicitly
+//     inverted M does not, and CG then stalls above small tolerances).
+//   * kmv_*: Q = (K + lam I) P, the product that dominates each iteration:
+//     K is streamed once from HBM as float4 rows.  Because K is symmetric,
+//     Q[i] = sum_j K[j][i] P[j]: lane l of a wave owns columns 4l..4l+3 of a
+//     1024-wide column block and walks the rows j of its row split; P[j][:]
+//     is the same for the whole wave, so it arrives through scalar loads and
+//     feeds the FMAs as a scalar operand.  Row splits write partial sums,
+//     reduced in a fixed order by the next kernel (which also adds lam P and
+//     the per-workgroup partials of p.q).
+//   * CG vector steps; every dot product is reduced in a fixed order (per
+//     workgroup partials, then one pass), so results are reproducible.
+//     Per-column state (gamma, beta, active flag, iteration count, relative
+//     residual) lives in device memory; a column that meets the tolerance
+//     is frozen (alpha = beta = 0 from then on).
+#include <float.h>
+#include <limits.h>
+
+#include "nk_kernels.h"
+
+namespace nk {
+
+constexpr int PC_TPB = 256;
+constexpr double kNegInf = -__builtin_huge_val();
+
+__device__ __forceinline__ bool pc_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// Deterministic (value, index) maximum over a 256-thread workgroup.
+__device__ inline void pc_block_argmax(double& v, int& i) {
+  __shared__ double sv[PC_TPB];
+  __shared__ int si[PC_TPB];
+  const int t = threadIdx.x;
+  sv[t] = v;
+  si[t] = i;
+  __syncthreads();
+  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+    if (t < w && pc_better(sv[t + w], si[t + w], sv[t], si[t])) {
+      sv[t] = sv[t + w];
+      si[t] = si[t + w];
+    }
+    __syncthreads();
+  }
+  v = sv[0];
+  i = si[0];
+  __syncthreads();
+}
+
+// d = diag(K); per-workgroup maximum of d.
+__global__ __launch_bounds__(PC_TPB) void pchol_init_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
+                                                            double* __restrict__ d, double* __restrict__ pv,
+                                                            int* __restrict__ pi) {
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  double v = -DBL_MAX;
+  int idx = INT_MAX;
+  if (i < n) {
+    v = (double)K[i * ldk + i];
+    d[i] = v;
+    idx = (int)i;
+  }
+  pc_block_argmax(v, idx);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = v;
+    pi[blockIdx.x] = idx;
+  }
+}
+
+// Pivot step m: column m of L (column major, leading dim n) and the update of d.
+__global__ __launch_bounds__(PC_TPB) void pchol_step_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
+                                                            double* __restrict__ L, int m, double* __restrict__ d,
+                                                            const double* __restrict__ pv_in,
+                                                            const int* __restrict__ pi_in, int nb,
+                                                            double* __restrict__ pv_out, int* __restrict__ pi_out,
+                                                            int* __restrict__ piv, double* __restrict__ dpiv,
+                                                            double pivot_tol) {
+  extern __shared__ double lp[];  // L[p][0..m)
+  const int t = threadIdx.x;
+  double v = -DBL_MAX;
+  int idx = INT_MAX;
+  for (int b = t; b < nb; b += PC_TPB) {
+    if (pc_better(pv_in[b], pi_in[b], v, idx)) {
+      v = pv_in[b];
+      idx = pi_in[b];
+    }
+  }
+  pc_block_argmax(v, idx);
+  const double dmax = v;
+  const int p = idx;
+  const double dmax0 = m == 0 ? dmax : dpiv[0];
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + t;
+  if (!(dmax > 0.0) || dmax <= pivot_tol * dmax0 || p >= n) {
+    // rank reached: zero column, and pass the same maximum on so that every
+    // later step stops too
+    if (i < n) L[(int64_t)m * n + i] = 0.0;
+    if (t == 0) {
+      pv_out[blockIdx.x] = dmax;
+      pi_out[blockIdx.x] = p;
+      if (blockIdx.x == 0) {
+        piv[m] = -1;
+        dpiv[m] = 0.0;
+      }
+    }
+    return;
+  }
+  for (int k = t; k < m; k += PC_TPB) lp[k] = L[(int64_t)k * n + p];
+  __syncthreads();
+  const double sp = sqrt(dmax);
+  double nv = -DBL_MAX;
+  int nidx = INT_MAX;
+  if (i < n) {
+    double di = d[i];
+    double l;
+    if (i == p) {
+      l = sp;
+      di = kNegInf;
+    } else if (di == kNegInf) {
+      l = 0.0;
+    } else {
+      double acc = 0.0;
+      for (int k = 0; k < m; ++k) acc = fma(L[(int64_t)k * n + i], lp[k], acc);
+      l = ((double)K[(int64_t)p * ldk + i] - acc) / sp;
+      di -= l * l;
+    }
+    L[(int64_t)m * n + i] = l;
+    d[i] = di;
+    nv = di;
+    nidx = (int)i;
+  }
+  pc_block_argmax(nv, nidx);
+  if (t == 0) {
+    pv_out[blockIdx.x] = nv;
+    pi_out[blockIdx.x] = nidx;
+    if (blockIdx.x == 0) {
+      piv[m] = p;
+      dpiv[m] = dmax;
+    }
+  }
+}
+
+int launch_pchol(const float* K, int64_t n, int64_t ldk, int rank, double pivot_tol, double* L, int* piv,
+                 double* d, double* pv, int* pi, double* dpiv, hipStream_t s) {
+  const int nb = (int)((n + PC_TPB - 1) / PC_TPB);
+  hipLaunchKernelGGL(pchol_init_kernel, dim3(nb), dim3(PC_TPB), 0, s, K, n, ldk, d, pv, pi);
+  for (int m = 0; m < rank; ++m) {
+    const int a = m & 1, b = a ^ 1;
+    hipLaunchKernelGGL(pchol_step_kernel, dim3(nb), dim3(PC_TPB), (size_t)(m > 0 ? m : 1) * sizeof(double), s, K,
+                       n, ldk, L, m, d, pv + (size_t)a * nb, pi + (size_t)a * nb, nb, pv + (size_t)b * nb,
+                       pi + (size_t)b * nb, piv, dpiv, pivot_tol);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ---- preconditioner set-up ----------------------------------------------
+
+// Lr (n x r, row major) <- L (n x r, column major)
+__global__ __launch_bounds__(PC_TPB) void pc_transpose_kernel(const double* __restrict__ L, int64_t n, int r,
+                                                              double* __restrict__ Lr) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int a0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int a = a0 + y;
+    const int64_t i = i0 + tx;
+    tile[y][tx] = (a < r && i < n) ? L[(int64_t)a * n + i] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t i = i0 + y;
+    const int a = a0 + tx;
+    if (a < r && i < n) Lr[i * r + a] = tile[tx][y];
+  }
+}
+
+// M = lam I + L^T L (r x r, row major), 32 x 32 output tiles; also clears the
+// factorisation flag.
+__global__ __launch_bounds__(PC_TPB) void pc_ltl_kernel(const double* __restrict__ L, int64_t n, int r, double lam,
+                                                        double* __restrict__ M, int* __restrict__ info) {
+  __shared__ double A[32][33], B[32][33];
+  const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of threads, 4 outputs each
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = 0; i0 < n; i0 += 32) {
+    for (int y = ty; y < 32; y += 8) {
+      const int64_t i = i0 + tx;
+      A[y][tx] = (a0 + y < r && i < n) ? L[(int64_t)(a0 + y) * n + i] : 0.0;
+      B[y][tx] = (b0 + y < r && i < n) ? L[(int64_t)(b0 + y) * n + i] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < 32; ++k) {
+      const double bv = B[tx][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(A[ty + 8 * q][k], bv, acc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = a0 + ty + 8 * q, b = b0 + tx;
+    if (a < r && b < r) M[(int64_t)a * r + b] = acc[q] + (a == b ? lam : 0.0);
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) info[0] = 0;
+}
+
+// U = L R^{-T} in place (L column major n x r; R the lower Cholesky factor of
+// M, stored in M's lower triangle): row i of U solves R u = l_i by forward
+// substitution, one thread per row.
+__global__ __launch_bounds__(PC_TPB) void pc_u_kernel(double* __restrict__ LU, int64_t n, int r,
+                                                      const double* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  if (i >= n) return;
+  for (int a = 0; a < r; ++a) {
+    const double* ra = R + (int64_t)a * r;
+    double s = LU[(int64_t)a * n + i];
+    for (int b = 0; b < a; ++b) s = fma(-ra[b], LU[(int64_t)b * n + i], s);
+    LU[(int64_t)a * n + i] = s / ra[a];
+  }
+}
+
+int launch_pc_setup(double* LU, int64_t n, int r, double lam, double* Ur, double* M, int* info, hipStream_t s) {
+  if (r == 0) return 0;
+  const unsigned g = (unsigned)((r + 31) / 32);
+  hipLaunchKernelGGL(pc_ltl_kernel, dim3(g, g), dim3(PC_TPB), 0, s, LU, n, r, lam, M, info);
+  if (launch_cholesky(M, r, info, s)) return -3;
+  hipLaunchKernelGGL(pc_u_kernel, dim3((unsigned)((n + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0, s, LU, n, r, M);
+  hipLaunchKernelGGL(pc_transpose_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((r + 31) / 32)), dim3(PC_TPB),
+                     0, s, LU, n, r, Ur);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ---- Q = (K + lam I) P ----------------------------------------------------
+
+constexpr int KMV_COLS = 1024;  // columns of K per workgroup (4 waves x 64 lanes x 4)
+
+// Partial sums over rows [j0, j1) of K for the 1024 columns of this block:
+// part[s][i][c] = sum_j K[j][i] P[j][c].
+template <int C, bool VEC>
+__global__ __launch_bounds__(PC_TPB) void kmv_partial_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
+                                                             const double* __restrict__ P, int64_t rows_per_split,
+                                                             double* __restrict__ part) {
+  const int64_t i0 = (int64_t)blockIdx.x * KMV_COLS + 4 * threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t j1 = j0 + rows_per_split < n ? j0 + rows_per_split : n;
+  double acc[4][C];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[e][c] = 0.0;
+  if (i0 < n && j0 < j1) {
+    if (VEC) {
+      // four rows per step, all four loads issued before their FMAs
+      const float* kb = K + i0;
+      int64_t j = j0;
+      for (; j + 4 <= j1; j += 4) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4*>(kb + (j + u) * ldk);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float kv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+          const double* pr = P + (j + u) * C;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double kd = (double)kv[e];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[e][c] = fma(kd, pr[c], acc[e][c]);
+          }
+        }
+      }
+      for (; j < j1; ++j) {
+        const float4 v = *reinterpret_cast<const float4*>(kb + j * ldk);
+        const float kv[4] = {v.x, v.y, v.z, v.w};
+        const double* pr = P + j * C;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double kd = (double)kv[e];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[e][c] = fma(kd, pr[c], acc[e][c]);
+        }
+      }
+    } else {
+      const float* kp = K + j0 * ldk + i0;
+      for (int64_t j = j0; j < j1; ++j, kp += ldk) {
+        float kv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) kv[e] = i0 + e < n ? kp[e] : 0.f;
+        const double* pr = P + j * C;
+        double pj[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) pj[c] = pr[c];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double kd = (double)kv[e];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[e][c] = fma(kd, pj[c], acc[e][c]);
+        }
+      }
+    }
+  }
+  double* out = part + (int64_t)blockIdx.y * n * C;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (i0 + e < n) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[(i0 + e) * C + c] = acc[e][c];
+    }
+  }
+}
+
+// Q[i] = sum_s part[s][i] + lam P[i]; per-workgroup partials of p.q per column.
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void kmv_reduce_kernel(const double* __restrict__ part, int S, int64_t n,
+                                                            const double* __restrict__ P, double lam,
+                                                            double* __restrict__ Q, double* __restrict__ pq_part) {
+  __shared__ double red[PC_TPB];
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  double q[C], d[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    q[c] = 0.0;
+    d[c] = 0.0;
+  }
+  if (i < n) {
+    for (int s = 0; s < S; ++s) {
+      const double* ps = part + ((int64_t)s * n + i) * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) q[c] += ps[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double pv = P[i * C + c];
+      q[c] = fma(lam, pv, q[c]);
+      Q[i * C + c] = q[c];
+      d[c] = pv * q[c];
+    }
+  }
+  for (int c = 0; c < C; ++c) {
+    red[threadIdx.x] = d[c];
+    __syncthreads();
+    for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) pq_part[(int64_t)blockIdx.x * C + c] = red[0];
+    __syncthreads();
+  }
+}
+
+// Row splits of the product: enough workgroups to fill the chip, at least
+// 64 rows each.
+int kmv_splits(int64_t n) {
+  const int64_t ncb = (n + KMV_COLS - 1) / KMV_COLS;
+  int64_t S = (1024 + ncb - 1) / ncb;
+  const int64_t maxS = (n + 63) / 64;
+  if (S > maxS) S = maxS;
+  if (S > 64) S = 64;
+  return (int)(S < 1 ? 1 : S);
+}
+
+template <int C>
+int launch_kmv_c(const float* K, int64_t n, int64_t ldk, const double* P, double lam, double* part, double* Q,
+                 double* pq_part, hipStream_t s, ProfHook* hook) {
+  const int S = kmv_splits(n);
+  const int64_t rows = (n + S - 1) / S;
+  const bool vec = (ldk % 4 == 0) && ((reinterpret_cast<uintptr_t>(K) & 15) == 0);
+  const dim3 grid((unsigned)((n + KMV_COLS - 1) / KMV_COLS), (unsigned)S);
+  if (hook) hook->begin(s);
+  if (vec)
+    hipLaunchKernelGGL((kmv_partial_kernel<C, true>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part);
+  else
+    hipLaunchKernelGGL((kmv_partial_kernel<C, false>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part);
+  if (hook) hook->end(s);
+  hipLaunchKernelGGL((kmv_reduce_kernel<C>), dim3((unsigned)((n + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0, s, part,
+                     S, n, P, lam, Q, pq_part);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ---- CG vector steps ------------------------------------------------------
+
+// Per-column state of a CG pass.
+struct PcgState {
+  double* gamma;   // r.z of the current residual
+  double* beta;    // last beta
+  double* ynorm;   // ||y||
+  double* relres;  // ||r|| / ||y|| at the column's last update
+  int* active;     // 1 while the column iterates
+  int* iters;      // updates taken
+};
+
+__device__ inline double pc_sum_parts(const double* __restrict__ part, int nb, int C, int c) {
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * C + c];
+  return s;
+}
+
+// Fixed-order block sum of one value per thread, written to out (thread 0).
+__device__ inline void pc_block_sum_store(double v, double* out) {
+  __shared__ double red[PC_TPB];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+  __syncthreads();
+}
+
+// R = Y[:, c0:c0+C], X = 0; partials of ||y||^2.
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pcg_init_kernel(const double* __restrict__ Y, int64_t ldy, int64_t c0,
+                                                          int64_t n, double* __restrict__ R, double* __restrict__ X,
+                                                          double* __restrict__ yy_part) {
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  double y[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) y[c] = 0.0;
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      y[c] = Y[i * ldy + c0 + c];
+      R[i * C + c] = y[c];
+      X[i * C + c] = 0.0;
+    }
+  }
+  for (int c = 0; c < C; ++c) pc_block_sum_store(y[c] * y[c], &yy_part[(int64_t)blockIdx.x * C + c]);
+}
+
+template <int C>
+__global__ __launch_bounds__(64) void pcg_init_state_kernel(const double* __restrict__ yy_part, int nb, PcgState st) {
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  const double yn = sqrt(pc_sum_parts(yy_part, nb, C, c));
+  st.ynorm[c] = yn;
+  st.active[c] = yn > 0.0 ? 1 : 0;
+  st.iters[c] = 0;
+  st.relres[c] = yn > 0.0 ? 1.0 : 0.0;
+  st.beta[c] = 0.0;
+}
+
+// W partial: wpart[s][a][c] = sum_{i in split s} Ur[i][a] V[i][c]  (one wave per block)
+template <int C>
+__global__ __launch_bounds__(64) void pc_lt_kernel(const double* __restrict__ Ur, int64_t n, int r,
+                                                   const double* __restrict__ V, int64_t rows_per_split,
+                                                   double* __restrict__ wpart) {
+  const int a = blockIdx.x * 64 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t i1 = i0 + rows_per_split < n ? i0 + rows_per_split : n;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  if (a < r) {
+    for (int64_t i = i0; i < i1; ++i) {
+      const double l = Ur[i * r + a];
+      const double* vr = V + i * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fma(l, vr[c], acc[c]);
+    }
+    double* o = wpart + ((int64_t)blockIdx.y * r + a) * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) o[c] = acc[c];
+  }
+}
+
+// W[a][c] = sum_s wpart[s][a][c]
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pc_w_reduce_kernel(const double* __restrict__ wpart, int S, int r,
+                                                             double* __restrict__ W) {
+  const int e = blockIdx.x * PC_TPB + threadIdx.x;
+  if (e >= r * C) return;
+  double s = 0.0;
+  for (int q = 0; q < S; ++q) s += wpart[(int64_t)q * r * C + e];
+  W[e] = s;
+}
+
+// Z[i] = (V[i] - sum_a U[a][i] W[a]) / lam; partials of v.z per column.
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pc_z_kernel(const double* __restrict__ U, int64_t n, int r,
+                                                      const double* __restrict__ W, const double* __restrict__ V,
+                                                      double lam, double* __restrict__ Z,
+                                                      double* __restrict__ vz_part) {
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  double d[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) d[c] = 0.0;
+  if (i < n) {
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    for (int a = 0; a < r; ++a) {
+      const double l = U[(int64_t)a * n + i];
+      const double* z = W + (int64_t)a * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fma(l, z[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const double v = V[i * C + c];
+      const double z = (v - acc[c]) / lam;
+      Z[i * C + c] = z;
+      d[c] = v * z;
+    }
+  }
+  for (int c = 0; c < C; ++c) pc_block_sum_store(d[c], &vz_part[(int64_t)blockIdx.x * C + c]);
+}
+
+// alpha = gamma / p.q for active columns (0 otherwise); X += alpha P,
+// R -= alpha Q; partials of ||r||^2.
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pcg_update_kernel(int64_t n, const double* __restrict__ pq_part, int nb,
+                                                            PcgState st, const double* __restrict__ P,
+                                                            const double* __restrict__ Q, double* __restrict__ X,
+                                                            double* __restrict__ R, double* __restrict__ rr_part) {
+  __shared__ double alpha[C];
+  if (threadIdx.x < C) {
+    const int c = threadIdx.x;
+    alpha[c] = st.active[c] ? st.gamma[c] / pc_sum_parts(pq_part, nb, C, c) : 0.0;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  double rr[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) rr[c] = 0.0;
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t e = i * C + c;
+      X[e] = fma(alpha[c], P[e], X[e]);
+      const double rv = fma(-alpha[c], Q[e], R[e]);
+      R[e] = rv;
+      rr[c] = rv * rv;
+    }
+  }
+  for (int c = 0; c < C; ++c) pc_block_sum_store(rr[c], &rr_part[(int64_t)blockIdx.x * C + c]);
+}
+
+// After the update of iteration `it`: residuals, stopping test, counts.
+template <int C>
+__global__ __launch_bounds__(64) void pcg_residual_kernel(const double* __restrict__ rr_part, int nb, PcgState st,
+                                                          int it, double tol) {
+  const int c = threadIdx.x;
+  if (c >= C || !st.active[c]) return;
+  const double rel = sqrt(pc_sum_parts(rr_part, nb, C, c)) / st.ynorm[c];
+  st.relres[c] = rel;
+  st.iters[c] = it + 1;
+  if (rel <= tol) st.active[c] = 0;
+}
+
+// gamma' = r.z; beta = gamma'/gamma for active columns (0 otherwise);
+// gamma <- gamma' for active columns.  first: gamma <- gamma' only.
+template <int C>
+__global__ __launch_bounds__(64) void pcg_beta_kernel(const double* __restrict__ rz_part, int nb, PcgState st,
+                                                      int first) {
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  const double g = pc_sum_parts(rz_part, nb, C, c);
+  if (first) {
+    st.gamma[c] = g;
+    st.beta[c] = 0.0;
+    return;
+  }
+  const bool act = st.active[c] != 0;
+  st.beta[c] = act ? g / st.gamma[c] : 0.0;
+  if (act) st.gamma[c] = g;
+}
+
+// P = Z + beta P  (first: P = Z)
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pcg_direction_kernel(int64_t n, PcgState st, const double* __restrict__ Z,
+                                                               double* __restrict__ P, int first) {
+  const int64_t e = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  if (e >= n * C) return;
+  const int c = (int)(e % C);
+  P[e] = first ? Z[e] : fma(st.beta[c], P[e], Z[e]);
+}
+
+// X[:, c0:c0+C] of the caller's n x ldx output
+template <int C>
+__global__ __launch_bounds__(PC_TPB) void pcg_store_kernel(int64_t n, const double* __restrict__ Xg,
+                                                           double* __restrict__ X, int64_t ldx, int64_t c0) {
+  const int64_t e = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+  if (e >= n * C) return;
+  const int64_t i = e / C;
+  const int c = (int)(e - i * C);
+  X[i * ldx + c0 + c] = Xg[e];
+}
+
+// One CG pass over a group of C <= 16 right-hand-side columns.
+template <int C>
+int pcg_group(const PcgArgs& a, int64_t c0, hipStream_t s) {
+  const int64_t n = a.n;
+  const int nb = (int)((n + PC_TPB - 1) / PC_TPB);
+  const unsigned gv = (unsigned)((n * C + PC_TPB - 1) / PC_TPB);
+  PcgState st{a.gamma, a.beta, a.ynorm, a.relres, a.active, a.iters};
+  // r-side split of L^T v
+  const int lt_splits = a.lt_splits;
+  const int64_t lt_rows = (n + lt_splits - 1) / lt_splits;
+
+  auto precond = [&](const double* V, double* Z, double* vz_part) {
+    if (a.r > 0) {
+      hipLaunchKernelGGL((pc_lt_kernel<C>), dim3((unsigned)((a.r + 63) / 64), (unsigned)lt_splits), dim3(64), 0, s,
+                         a.Ur, n, a.r, V, lt_rows, a.wpart);
+      hipLaunchKernelGGL((pc_w_reduce_kernel<C>), dim3((unsigned)((a.r * C + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0,
+                         s, a.wpart, lt_splits, a.r, a.W);
+    }
+    hipLaunchKernelGGL((pc_z_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, a.U, n, a.r, a.W, V, a.lam, Z, vz_part);
+  };
+
+  hipLaunchKernelGGL((pcg_init_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, a.Y, a.ldy, c0, n, a.R, a.X, a.part1);
+  hipLaunchKernelGGL((pcg_init_state_kernel<C>), dim3(1), dim3(64), 0, s, a.part1, nb, st);
+  precond(a.R, a.Z, a.part2);
+  hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(64), 0, s, a.part2, nb, st, 1);
+  hipLaunchKernelGGL((pcg_direction_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, st, a.Z, a.P, 1);
+  if (hipGetLastError() != hipSuccess) return -3;
+
+  int done_iters = 0;
+  for (int it = 0; it < a.max_iter; ++it) {
+    if (it > 0 && it % a.check_every == 0) {
+      int act[16];
+      if (hipMemcpyAsync(act, a.active, sizeof(int) * C, hipMemcpyDeviceToHost, s) != hipSuccess) return -3;
+      if (hipStreamSynchronize(s) != hipSuccess) return -3;
+      bool any = false;
+      for (int c = 0; c < C; ++c) any = any || act[c] != 0;
+      if (!any) break;
+    }
+    if (launch_kmv_c<C>(a.K, n, a.ldk, a.P, a.lam, a.kpart, a.Q, a.part1, s, a.hook)) return -3;
+    hipLaunchKernelGGL((pcg_update_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, n, a.part1, nb, st, a.P, a.Q, a.X, a.R,
+                       a.part2);
+    hipLaunchKernelGGL((pcg_residual_kernel<C>), dim3(1), dim3(64), 0, s, a.part2, nb, st, it, a.tol);
+    precond(a.R, a.Z, a.part1);
+    hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(64), 0, s, a.part1, nb, st, 0);
+    hipLaunchKernelGGL((pcg_direction_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, st, a.Z, a.P, 0);
+    if (hipGetLastError() != hipSuccess) return -3;
+    done_iters = it + 1;
+  }
+  (void)done_iters;
+  hipLaunchKernelGGL((pcg_store_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, a.X, a.Xout, a.ldx, c0);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_pcg_group(const PcgArgs& a, int64_t c0, int C, hipStream_t s) {
+  switch (C) {
+    case 1: return pcg_group<1>(a, c0, s);
+    case 2: return pcg_group<2>(a, c0, s);
+    case 3: return pcg_group<3>(a, c0, s);
+    case 4: return pcg_group<4>(a, c0, s);
+    case 5: return pcg_group<5>(a, c0, s);
+    case 6: return pcg_group<6>(a, c0, s);
+    case 7: return pcg_group<7>(a, c0, s);
+    case 8: return pcg_group<8>(a, c0, s);
+    case 9: return pcg_group<9>(a, c0, s);
+    case 10: return pcg_group<10>(a, c0, s);
+    case 11: return pcg_group<11>(a, c0, s);
+    case 12: return pcg_group<12>(a, c0, s);
+    case 13: return pcg_group<13>(a, c0, s);
+    case 14: return pcg_group<14>(a, c0, s);
+    case 15: return pcg_group<15>(a, c0, s);
+    case 16: return pcg_group<16>(a, c0, s);
+    default: return -1;
+  }
+}
+
+int launch_kmv(const float* K, int64_t n, int64_t ldk, const double* P, int C, double lam, double* part, double* Q,
+               double* pq_part, hipStream_t s, ProfHook* hook) {
+  switch (C) {
+#define NK_KMV_CASE(c) \
+  case c:              \
+    return launch_kmv_c<c>(K, n, ldk, P, lam, part, Q, pq_part, s, hook);
+    NK_KMV_CASE(1) NK_KMV_CASE(2) NK_KMV_CASE(3) NK_KMV_CASE(4) NK_KMV_CASE(5) NK_KMV_CASE(6) NK_KMV_CASE(7)
+    NK_KMV_CASE(8) NK_KMV_CASE(9) NK_KMV_CASE(10) NK_KMV_CASE(11) NK_KMV_CASE(12) NK_KMV_CASE(13)
+    NK_KMV_CASE(14) NK_KMV_CASE(15) NK_KMV_CASE(16)
+#undef NK_KMV_CASE
+    default:
+      return -1;
+  }
+}
+
+// out[0] = mean(diag K)
+__global__ __launch_bounds__(PC_TPB) void pc_diag_mean_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
+                                                              double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += PC_TPB) s += (double)K[i * ldk + i];
+  pc_block_sum_store(s, out);
+  if (threadIdx.x == 0) out[0] = out[0] / (double)n;
+}
+
+int launch_diag_mean(const float* K, int64_t n, int64_t ldk, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(pc_diag_mean_kernel, dim3(1), dim3(PC_TPB), 0, s, K, n, ldk, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace nk

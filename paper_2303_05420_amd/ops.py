@@ -179,6 +179,74 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
     return dx1, dx2, ds
 
 
+def _check_gram(k: torch.Tensor) -> tuple[int, int]:
+    """(n, ldk) of a float32 CUDA n x n matrix with unit column stride."""
+    if not isinstance(k, torch.Tensor) or not k.is_cuda or k.dtype != torch.float32:
+        raise TypeError("k must be a float32 CUDA tensor")
+    if k.dim() != 2 or k.shape[0] != k.shape[1] or k.stride(1) != 1 or k.stride(0) < k.shape[0]:
+        raise ValueError("k must be square with rows contiguous")
+    return int(k.shape[0]), int(k.stride(0))
+
+
+def pivoted_cholesky(k: torch.Tensor, rank: int, pivot_tol: float = 0.0):
+    """Greedy partial pivoted Cholesky K ~ L L^T (float64): returns (L as an
+    n x rank view of the column-major factor, piv (int32, -1 past the rank
+    reached), rank reached)."""
+    n, ldk = _check_gram(k)
+    rank = int(rank)
+    lcm = torch.zeros((max(rank, 0), n), dtype=torch.float64, device=k.device)
+    piv = torch.full((max(rank, 0),), -1, dtype=torch.int32, device=k.device)
+    used = ctypes.c_int32(0)
+    ws = workspace(workspace_size(_lib.NK_OP_PIVOTED_CHOL, None, n, max(rank, 0)), k.device)
+    rc = _lib.lib().nk_pivoted_cholesky(k.data_ptr(), n, ldk, rank, float(pivot_tol), lcm.data_ptr(),
+                                        piv.data_ptr(), ctypes.byref(used), ws.data_ptr(), ws.numel(),
+                                        _stream(k.device))
+    _lib.check(rc)
+    return lcm.t(), piv, int(used.value)
+
+
+def gram_matvec(k: torch.Tensor, p: torch.Tensor, lam: float = 0.0) -> torch.Tensor:
+    """Q = (K + lam I) P for a symmetric float32 K and float64 P (n x c, c <= 16)."""
+    n, ldk = _check_gram(k)
+    if not p.is_cuda or p.dtype != torch.float64 or not p.is_contiguous() or p.dim() != 2 or p.shape[0] != n:
+        raise TypeError("p must be a contiguous float64 CUDA (n, c) tensor")
+    c = int(p.shape[1])
+    q = torch.empty_like(p)
+    ws = workspace(workspace_size(_lib.NK_OP_GRAM_MATVEC, None, n, c), k.device)
+    rc = _lib.lib().nk_gram_matvec(k.data_ptr(), n, ldk, p.data_ptr(), c, float(lam), q.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream(k.device))
+    _lib.check(rc)
+    return q
+
+
+def krr_pcg(k: torch.Tensor, y: torch.Tensor, ridge: float, relative: bool = True, rank: int = 100,
+            tol: float = 1e-8, max_iter: int = 1000, pivot_tol: float = 0.0):
+    """Solve (K + lam I) X = Y by preconditioned CG in float64 (lam = ridge,
+    or ridge * mean diag K if relative).  Returns (X, iters, relres, stats)
+    with iters/relres numpy arrays and stats = {rank, iterations, lambda}."""
+    import numpy as np
+
+    n, ldk = _check_gram(k)
+    if not y.is_cuda or y.dtype != torch.float64 or not y.is_contiguous() or y.dim() != 2 or y.shape[0] != n:
+        raise TypeError("y must be a contiguous float64 CUDA (n, c) tensor")
+    c = int(y.shape[1])
+    cfg = _lib.PcgCfg()
+    cfg.rank = int(rank)
+    cfg.max_iter = int(max_iter)
+    cfg.tol = float(tol)
+    cfg.pivot_tol = float(pivot_tol)
+    x = torch.empty_like(y)
+    iters = np.zeros(c, dtype=np.int32)
+    relres = np.zeros(c, dtype=np.float64)
+    st = _lib.PcgStats()
+    ws = workspace(workspace_size(_lib.NK_OP_PCG, cfg, n, c), k.device)
+    rc = _lib.lib().nk_krr_pcg(k.data_ptr(), n, ldk, y.data_ptr(), c, float(ridge), 1 if relative else 0,
+                               ctypes.byref(cfg), x.data_ptr(), iters.ctypes.data, relres.ctypes.data,
+                               ctypes.byref(st), ws.data_ptr(), ws.numel(), _stream(k.device))
+    _lib.check(rc)
+    return x, iters, relres, {"rank": int(st.rank), "iterations": int(st.iterations), "lambda": float(st.lambda_)}
+
+
 def krr_mse_backward(k_ss: torch.Tensor, k_ts: torch.Tensor, y_s: torch.Tensor, y_t: torch.Tensor, ridge: float,
                      relative: bool = False):
     """Cotangents of L = mean((K_ts (K_ss + lam I)^{-1} Y_s - Y_t)^2) with lam

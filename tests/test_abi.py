@@ -126,3 +126,45 @@ def test_batched_validation():
     # no pass has been tuned in this process
     out = (_lib.BatchedCandidate * 4)()
     assert L.nk_myrtle_batched_tuning(ctypes.byref(cfg), out, 4, None) == _lib.NK_EINVAL
+
+
+def test_solver_workspace_and_validation():
+    L = _lib.lib()
+    p = ctypes.c_void_p(256)
+    cfg = _lib.PcgCfg(64, 100, 1e-8, 0.0)
+    a = L.nk_workspace_size(_lib.NK_OP_PCG, ctypes.byref(cfg), 1000, 10)
+    cfg0 = _lib.PcgCfg(0, 100, 1e-8, 0.0)
+    b = L.nk_workspace_size(_lib.NK_OP_PCG, ctypes.byref(cfg0), 1000, 10)
+    assert a > b > 0 and a - b >= 2 * 1000 * 64 * 8  # two copies of L
+    assert L.nk_workspace_size(_lib.NK_OP_PCG, None, 1000, 10) == 0
+    assert L.nk_workspace_size(_lib.NK_OP_PIVOTED_CHOL, None, 1000, 64) > 1000 * 8
+    assert L.nk_workspace_size(_lib.NK_OP_GRAM_MATVEC, None, 1000, 10) > 0
+    need = L.nk_workspace_size(_lib.NK_OP_PIVOTED_CHOL, None, 100, 10)
+    used = ctypes.c_int32(-7)
+    assert L.nk_pivoted_cholesky(None, 100, 100, 10, 0.0, p, p, ctypes.byref(used), p, need, None) == _lib.NK_EINVAL
+    assert L.nk_pivoted_cholesky(p, 100, 99, 10, 0.0, p, p, None, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_pivoted_cholesky(p, 100, 100, 101, 0.0, p, p, None, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_pivoted_cholesky(p, 100, 100, 10, -1.0, p, p, None, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_pivoted_cholesky(p, 100, 100, 10, 0.0, p, p, None, p, 64, None) == _lib.NK_EINVAL
+    assert "workspace" in L.nk_last_error().decode()
+    assert L.nk_pivoted_cholesky(p, 100, 100, 0, 0.0, None, None, ctypes.byref(used), None, 0, None) == _lib.NK_OK
+    assert used.value == 0
+    mv = L.nk_workspace_size(_lib.NK_OP_GRAM_MATVEC, None, 100, 16)
+    assert L.nk_gram_matvec(p, 100, 100, p, 17, 0.0, p, p, mv, None) == _lib.NK_EUNSUPPORTED
+    assert L.nk_gram_matvec(p, 100, 100, p, 0, 0.0, p, p, mv, None) == _lib.NK_EUNSUPPORTED
+    assert L.nk_gram_matvec(p, 100, 100, p, 4, 0.0, p, p, 8, None) == _lib.NK_EINVAL
+    ws = L.nk_workspace_size(_lib.NK_OP_PCG, ctypes.byref(cfg), 100, 10)
+    st = _lib.PcgStats()
+    assert L.nk_krr_pcg(p, 100, 100, p, 10, 1e-3, 0, None, p, None, None, None, p, ws, None) == _lib.NK_EINVAL
+    bad = _lib.PcgCfg(64, 0, 1e-8, 0.0)
+    assert L.nk_krr_pcg(p, 100, 100, p, 10, 1e-3, 0, ctypes.byref(bad), p, None, None, None, p, ws,
+                        None) == _lib.NK_EINVAL
+    bad = _lib.PcgCfg(64, 10, -1.0, 0.0)
+    assert L.nk_krr_pcg(p, 100, 100, p, 10, 1e-3, 0, ctypes.byref(bad), p, None, None, None, p, ws,
+                        None) == _lib.NK_EINVAL
+    assert L.nk_krr_pcg(p, 100, 100, p, 10, 1e-3, 0, ctypes.byref(cfg), p, None, None, ctypes.byref(st), p, 64,
+                        None) == _lib.NK_EINVAL
+    # lambda = 0 is rejected before any device work
+    assert L.nk_krr_pcg(p, 100, 100, p, 10, 0.0, 0, ctypes.byref(cfg), p, None, None, ctypes.byref(st), p, ws,
+                        None) == _lib.NK_EINVAL
+    assert "lambda" in L.nk_last_error().decode()
