@@ -43,6 +43,7 @@ def _args():
     p.add_argument("--no-fwd-bwd", action="store_true", help="skip the fwd+bwd measurement")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain tile comparison")
     p.add_argument("--no-ntk", action="store_true", help="skip the Myrtle-10 NTK measurement")
+    p.add_argument("--no-pcg", action="store_true", help="skip the preconditioned-CG solve measurement")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -181,6 +182,102 @@ def _batched(torch, full: bool):
             "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands)}
 
 
+def _pcg(torch, cpu: bool):
+    """Kernel regression by FP64 preconditioned CG on a 32768 x 32768 float32
+    Gram (FC-3 NNGP of the workload's images, built on the GPU before the
+    timed region), 10 targets, rank-512 pivoted-Cholesky preconditioner,
+    tol 1e-8: one untimed solve, one timed solve, then 20 profiled K.P
+    products for the HBM roofline.  With cpu, the FP64 oracle solves the
+    leading 4096 x 4096 sub-system of the same K on the host, beside the GPU
+    solve of that sub-system."""
+    import numpy as np
+
+    import synth
+    from paper_2303_05420_amd import _lib, ops
+
+    w = synth.WORKLOADS["fc3_pcg_32768"]
+    n = w["n"]
+    xs = synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][0])
+    y = torch.from_numpy(synth.teacher_labels(xs, w["n_classes"], w["seeds"][1]).astype(np.float64)).cuda()
+    k = ops.fc_nngp(torch.from_numpy(xs.reshape(n, -1)).cuda(), None, w["fc_depth"], w["fc_sigma_w2"],
+                    w["fc_sigma_b2"])
+    kt = k.t().contiguous()
+    k.add_(kt).mul_(0.5)  # exactly symmetric (the solver reads rows as columns)
+    del kt
+
+    def solve(kk, yy):
+        return ops.krr_pcg(kk, yy, w["ridge_rel"], True, rank=w["rank"], tol=w["tol"], max_iter=w["max_iter"])
+
+    solve(k, y)
+    torch.cuda.synchronize()
+    print("pcg warm-up done", file=sys.stderr, flush=True)
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    x, iters, relres, st = solve(k, y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    print(f"pcg: {dt * 1e3:.1f} ms, {int(iters.max())} iterations", file=sys.stderr, flush=True)
+
+    p = torch.randn(n, w["n_classes"], dtype=torch.float64, device="cuda")
+    ops.gram_matvec(k, p, st["lambda"])
+    torch.cuda.synchronize()
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    for _ in range(20):
+        ops.gram_matvec(k, p, st["lambda"])
+    torch.cuda.synchronize()
+    _lib.profile_enable(False)
+    mv = _lib.profile_read(reset=True)["gram_matvec"]
+    mv_ms = mv[1] / mv[0]
+    bytes_per_launch = 4.0 * n * n  # each float32 entry of K read once
+    achieved = bytes_per_launch / (mv_ms / 1e3) / 1e9
+    setup_ms = sum(prof.get(kk, (0, 0.0))[1] for kk in ("pivoted_cholesky", "pcg_precond_setup"))
+    it_max = int(iters.max())
+    out = {"workload": f"kernel ridge regression, FP64 preconditioned CG on a {n}x{n} float32 Gram "
+                       f"(FC-3 NNGP of 32x32x3 correlated images), {w['n_classes']} one-hot targets, "
+                       f"ridge {w['ridge_rel']} mean diag, pivoted-Cholesky rank {w['rank']}, tol {w['tol']}",
+           "n": n, "targets": w["n_classes"], "rank": st["rank"], "tol": w["tol"], "iterations": it_max,
+           "max_relres": float(relres.max()), "solve_ms": round(dt * 1e3, 3),
+           "setup_ms": round(setup_ms, 3), "ms_per_iteration": round((dt * 1e3 - setup_ms) / max(it_max, 1), 4),
+           "kernels_ms": {kk: round(v[1], 3) for kk, v in prof.items()},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(achieved / 8000.0, 4), "traffic": None,
+                        "kernel": f"kmv_partial_kernel<{w['n_classes']}, true> (K.P)",
+                        "avg_launch_ms": round(mv_ms, 4), "algorithmic_bytes_per_launch": bytes_per_launch}}
+    if cpu:
+        from oracle import solvers
+
+        m = w["cpu_n"]
+        ks = k[:m, :m].contiguous()
+        ys = y[:m].contiguous()
+        solve(ks, ys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xg, ig, _, sg = solve(ks, ys)
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        k64 = ks.cpu().numpy().astype(np.float64)
+        y64 = ys.cpu().numpy()
+        t0 = time.perf_counter()
+        ref = solvers.pcg(k64, y64, solvers.ridge_lambda(k64, w["ridge_rel"], True), w["rank"], w["tol"],
+                          w["max_iter"])
+        cdt = time.perf_counter() - t0
+        err = float(np.max(np.abs(xg.cpu().numpy() - ref["X"])) / np.max(np.abs(ref["X"])))
+        out["cpu_baseline"] = {"value": round(cdt * 1e3, 1), "unit": "ms per solve", "kind": "oracle",
+                               "cores": min(16, len(os.sched_getaffinity(0))),
+                               "sample": f"leading {m}x{m} sub-system of the same K and targets, same settings "
+                                         f"({int(ref['iters'].max())} iterations, numpy float64)",
+                               "gpu_ms_same_sample": round(gdt * 1e3, 3),
+                               "gpu_iterations_same_sample": int(ig.max()),
+                               "max_rel_diff_x_vs_oracle": err}
+        print(f"pcg sample {m}: gpu {gdt * 1e3:.1f} ms, oracle {cdt * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    del k
+    return out
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -267,6 +364,7 @@ def main():
     fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
     batched = None if a.no_batched else _batched(torch, a.batched_full)
     ntk = None if a.no_ntk else _ntk(torch)
+    pcg = None if a.no_pcg else _pcg(torch, not a.no_cpu_baseline)
 
     cpu = None
     parity = None
@@ -315,6 +413,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched_tiles": batched,
         "ntk": ntk,
+        "pcg": pcg,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))

@@ -559,12 +559,12 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
 constexpr int kPcgMaxRank = 8192;  // LDS of a pivot step holds one row of L
 constexpr int kPcgGroup = 16;      // right-hand sides per CG pass
 
-// Row splits of L^T v: about 1024 single-wave workgroups, >= 64 rows each.
+// Row splits of U^T v: about 512 four-wave workgroups, >= 256 rows each.
 int pc_lt_splits(int64_t n, int r) {
   if (r <= 0) return 1;
   const int64_t g = (r + 63) / 64;
-  int64_t S = (1024 + g - 1) / g;
-  S = std::min<int64_t>(S, (n + 63) / 64);
+  int64_t S = (512 + g - 1) / g;
+  S = std::min<int64_t>(S, (n + 255) / 256);
   return (int)std::max<int64_t>(S, 1);
 }
 
@@ -578,7 +578,7 @@ struct PcgPlan {
 PcgPlan pcg_plan(int64_t n, int r, int what) {
   PcgPlan p{};
   Bump b;
-  const int64_t nb = (n + 255) / 256;
+  const int64_t nb = (n + 255) / 256, nbz = (n + 63) / 64;
   const size_t G = kPcgGroup;
   if (what != 2) {
     p.d = b.take(sizeof(double) * n);
@@ -601,12 +601,12 @@ PcgPlan pcg_plan(int64_t n, int r, int what) {
     p.Z = b.take(sizeof(double) * n * G);
     p.P = b.take(sizeof(double) * n * G);
     p.Q = b.take(sizeof(double) * n * G);
-    p.part2 = b.take(sizeof(double) * nb * G);
-    p.st = b.take(sizeof(double) * 6 * G);
+    p.part2 = b.take(sizeof(double) * nbz * G);
+    p.st = b.take(sizeof(double) * 7 * G);
   }
   if (what != 0) {
     p.kpart = b.take(sizeof(double) * (size_t)nk::kmv_splits(n) * n * G);
-    p.part1 = b.take(sizeof(double) * nb * G);
+    p.part1 = b.take(sizeof(double) * nbz * G);
   }
   p.total = b.off + 256;
   return p;
@@ -1125,7 +1125,6 @@ int nk_krr_pcg(const float* K, int64_t n, int64_t ldk, const double* Y, int64_t 
   a.lam = lam;
   a.tol = cfg->tol;
   a.max_iter = cfg->max_iter;
-  a.check_every = n >= 8192 ? 1 : 4;
   a.r = r;
   a.U = L;  // L R^{-T}, formed in place by the set-up
   a.Ur = at<double>(ws, pp.Lr);
@@ -1147,6 +1146,15 @@ int nk_krr_pcg(const float* K, int64_t n, int64_t ldk, const double* Y, int64_t 
   a.relres = st + 3 * kPcgGroup;
   a.active = reinterpret_cast<int*>(st + 4 * kPcgGroup);
   a.iters = reinterpret_cast<int*>(st + 5 * kPcgGroup);
+  a.any = reinterpret_cast<int*>(st + 6 * kPcgGroup);
+  int* host_any = nullptr;
+  if (hipHostMalloc((void**)&host_any, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return hip_fail("pinned flags");
+  struct PinnedFree {
+    int* p;
+    ~PinnedFree() { (void)hipHostFree(p); }
+  } pinned_free{host_any};
+  a.host_any = host_any;
   ScopeHook hook("pcg_matvec");
   a.hook = &hook;
   int max_it = 0;

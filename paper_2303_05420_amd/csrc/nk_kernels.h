@@ -154,7 +154,7 @@ struct PcgArgs {
   double* Xout;     // n x ldx
   int64_t ldx;
   double lam, tol;
-  int max_iter, check_every;
+  int max_iter;
   int r;                 // preconditioner rank (0: Ph = lam I)
   const double* U;       // n x r, column major: L R^{-T}, R R^T = lam I + L^T L
   const double* Ur;      // the same, row major
@@ -163,9 +163,11 @@ struct PcgArgs {
   int lt_splits;
   double *R, *X, *Z, *P, *Q;  // n x 16
   double* kpart;              // kmv_splits(n) x n x 16
-  double *part1, *part2;      // ceil(n / 256) x 16
+  double *part1, *part2;      // ceil(n / 64) x 16 (per-workgroup partial sums)
   double *gamma, *beta, *ynorm, *relres;  // 16 each
   int *active, *iters;                    // 16 each
+  int* any;                               // 1 device int: some column still iterates
+  int* host_any;                          // 3 ints of pinned host memory
   ProfHook* hook;
 };
 

@@ -67,6 +67,65 @@ __device__ inline void pc_block_argmax(double& v, int& i) {
   __syncthreads();
 }
 
+// Fixed-order column sums by the PC_TPB threads of a workgroup: out[c] =
+// sum_b part[b][c] (b < nb, c < C), through `red` (PC_TPB x C doubles of
+// LDS); every thread sees out after the call.
+template <int C>
+__device__ inline void pc_colsum(const double* __restrict__ part, int nb, double* red, double* out) {
+  const int t = threadIdx.x;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  for (int b = t; b < nb; b += PC_TPB) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += part[(int64_t)b * C + c];
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) red[t * C + c] = acc[c];
+  __syncthreads();
+  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[t * C + c] += red[(t + w) * C + c];
+    }
+    __syncthreads();
+  }
+  if (t < C) out[t] = red[t];
+  __syncthreads();
+}
+
+// Fixed-order workgroup sums of one value per thread and column, written to
+// out[0..C) (global), through `red` (PC_TPB x C doubles of LDS).
+template <int C>
+__device__ inline void pc_block_sums(const double (&v)[C], double* red, double* __restrict__ out) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < C; ++c) red[t * C + c] = v[c];
+  __syncthreads();
+  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[t * C + c] += red[(t + w) * C + c];
+    }
+    __syncthreads();
+  }
+  if (t < C) out[t] = red[t];
+  __syncthreads();
+}
+
+// Fixed-order block sum of one value per thread, written to out (thread 0).
+__device__ inline void pc_block_sum_store(double v, double* out) {
+  __shared__ double red[PC_TPB];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+  __syncthreads();
+}
+
 // d = diag(K); per-workgroup maximum of d.
 __global__ __launch_bounds__(PC_TPB) void pchol_init_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
                                                             double* __restrict__ d, double* __restrict__ pv,
@@ -138,6 +197,7 @@ __global__ __launch_bounds__(PC_TPB) void pchol_step_kernel(const float* __restr
       l = 0.0;
     } else {
       double acc = 0.0;
+#pragma unroll 8
       for (int k = 0; k < m; ++k) acc = fma(L[(int64_t)k * n + i], lp[k], acc);
       l = ((double)K[(int64_t)p * ldk + i] - acc) / sp;
       di -= l * l;
@@ -194,13 +254,20 @@ __global__ __launch_bounds__(PC_TPB) void pc_transpose_kernel(const double* __re
 }
 
 // M = lam I + L^T L (r x r, row major), 32 x 32 output tiles; also clears the
-// factorisation flag.
+// factorisation flag.  The Woodbury form subtracts L M^{-1} L^T from the
+// identity, which along the leading directions of K leaves only about
+// lam / sigma^2 (sigma^2 up to the largest eigenvalue of K): so M has to
+// match L^T L to about one rounding of its entries, or the preconditioner
+// loses definiteness there and CG stalls.  A plain running sum over n rows
+// is off by up to n roundings; the sums here carry their error terms
+// (exact product errors by FMA, TwoSum for the additions) and round once.
 __global__ __launch_bounds__(PC_TPB) void pc_ltl_kernel(const double* __restrict__ L, int64_t n, int r, double lam,
                                                         double* __restrict__ M, int* __restrict__ info) {
+#pragma clang fp contract(off)
   __shared__ double A[32][33], B[32][33];
   const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of threads, 4 outputs each
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double hi[4] = {0.0, 0.0, 0.0, 0.0}, lo[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t i0 = 0; i0 < n; i0 += 32) {
     for (int y = ty; y < 32; y += 8) {
       const int64_t i = i0 + tx;
@@ -211,14 +278,33 @@ __global__ __launch_bounds__(PC_TPB) void pc_ltl_kernel(const double* __restrict
     for (int k = 0; k < 32; ++k) {
       const double bv = B[tx][k];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = fma(A[ty + 8 * q][k], bv, acc[q]);
+      for (int q = 0; q < 4; ++q) {
+        const double av = A[ty + 8 * q][k];
+        const double p = av * bv;
+        const double pe = __builtin_fma(av, bv, -p);  // av bv - p exactly
+        const double s = hi[q] + p;
+        const double bb = s - hi[q];
+        const double se = (hi[q] - (s - bb)) + (p - bb);  // hi + p - s exactly
+        hi[q] = s;
+        lo[q] += se + pe;
+      }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int a = a0 + ty + 8 * q, b = b0 + tx;
-    if (a < r && b < r) M[(int64_t)a * r + b] = acc[q] + (a == b ? lam : 0.0);
+    if (a < r && b < r) {
+      double v = hi[q];
+      double e = lo[q];
+      if (a == b) {
+        const double s = v + lam;
+        const double bb = s - v;
+        e += (v - (s - bb)) + (lam - bb);
+        v = s;
+      }
+      M[(int64_t)a * r + b] = v + e;
+    }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) info[0] = 0;
 }
@@ -252,13 +338,20 @@ int launch_pc_setup(double* LU, int64_t n, int r, double lam, double* Ur, double
 // ---- Q = (K + lam I) P ----------------------------------------------------
 
 constexpr int KMV_COLS = 1024;  // columns of K per workgroup (4 waves x 64 lanes x 4)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Partial sums over rows [j0, j1) of K for the 1024 columns of this block:
 // part[s][i][c] = sum_j K[j][i] P[j][c].
+// A kernel of a conjugate-gradient iteration returns at once when its gate
+// (the solver's "some column still iterates" flag) reads 0.
+#define NK_PCG_GATE(g) \
+  if ((g) != nullptr && *(g) == 0) return;
+
 template <int C, bool VEC>
 __global__ __launch_bounds__(PC_TPB) void kmv_partial_kernel(const float* __restrict__ K, int64_t n, int64_t ldk,
                                                              const double* __restrict__ P, int64_t rows_per_split,
-                                                             double* __restrict__ part) {
+                                                             double* __restrict__ part, const int* __restrict__ gate) {
+  NK_PCG_GATE(gate)
   const int64_t i0 = (int64_t)blockIdx.x * KMV_COLS + 4 * threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t j1 = j0 + rows_per_split < n ? j0 + rows_per_split : n;
@@ -269,13 +362,18 @@ __global__ __launch_bounds__(PC_TPB) void kmv_partial_kernel(const float* __rest
     for (int c = 0; c < C; ++c) acc[e][c] = 0.0;
   if (i0 < n && j0 < j1) {
     if (VEC) {
-      // four rows per step, all four loads issued before their FMAs
+      // four rows per step, all four loads issued before their FMAs; K is
+      // read once per product, so its loads are non-temporal (they do not
+      // evict P from the caches)
       const float* kb = K + i0;
       int64_t j = j0;
       for (; j + 4 <= j1; j += 4) {
         float4 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const float4*>(kb + (j + u) * ldk);
+        for (int u = 0; u < 4; ++u) {
+          const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(kb + (j + u) * ldk));
+          v[u] = make_float4(t.x, t.y, t.z, t.w);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const float kv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -332,8 +430,10 @@ __global__ __launch_bounds__(PC_TPB) void kmv_partial_kernel(const float* __rest
 template <int C>
 __global__ __launch_bounds__(PC_TPB) void kmv_reduce_kernel(const double* __restrict__ part, int S, int64_t n,
                                                             const double* __restrict__ P, double lam,
-                                                            double* __restrict__ Q, double* __restrict__ pq_part) {
-  __shared__ double red[PC_TPB];
+                                                            double* __restrict__ Q, double* __restrict__ pq_part,
+                                                            const int* __restrict__ gate) {
+  NK_PCG_GATE(gate)
+  __shared__ double red[PC_TPB * C];
   const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
   double q[C], d[C];
 #pragma unroll
@@ -342,6 +442,7 @@ __global__ __launch_bounds__(PC_TPB) void kmv_reduce_kernel(const double* __rest
     d[c] = 0.0;
   }
   if (i < n) {
+#pragma unroll 4
     for (int s = 0; s < S; ++s) {
       const double* ps = part + ((int64_t)s * n + i) * C;
 #pragma unroll
@@ -355,23 +456,15 @@ __global__ __launch_bounds__(PC_TPB) void kmv_reduce_kernel(const double* __rest
       d[c] = pv * q[c];
     }
   }
-  for (int c = 0; c < C; ++c) {
-    red[threadIdx.x] = d[c];
-    __syncthreads();
-    for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) pq_part[(int64_t)blockIdx.x * C + c] = red[0];
-    __syncthreads();
-  }
+  pc_block_sums<C>(d, red, pq_part + (int64_t)blockIdx.x * C);
 }
 
-// Row splits of the product: enough workgroups to fill the chip, at least
-// 64 rows each.
+// Row splits of the product: about 512 workgroups (8 waves per CU, each with
+// four rows in flight), at least 64 rows each.  Measured on a 32768 x 32768
+// K: 16 splits stream at 6.5-6.7 TB/s, 32 at 6.0, 64 at 5.5, 8 at 4.8.
 int kmv_splits(int64_t n) {
   const int64_t ncb = (n + KMV_COLS - 1) / KMV_COLS;
-  int64_t S = (1024 + ncb - 1) / ncb;
+  int64_t S = (512 + ncb - 1) / ncb;
   const int64_t maxS = (n + 63) / 64;
   if (S > maxS) S = maxS;
   if (S > 64) S = 64;
@@ -380,19 +473,19 @@ int kmv_splits(int64_t n) {
 
 template <int C>
 int launch_kmv_c(const float* K, int64_t n, int64_t ldk, const double* P, double lam, double* part, double* Q,
-                 double* pq_part, hipStream_t s, ProfHook* hook) {
+                 double* pq_part, const int* gate, hipStream_t s, ProfHook* hook) {
   const int S = kmv_splits(n);
   const int64_t rows = (n + S - 1) / S;
   const bool vec = (ldk % 4 == 0) && ((reinterpret_cast<uintptr_t>(K) & 15) == 0);
   const dim3 grid((unsigned)((n + KMV_COLS - 1) / KMV_COLS), (unsigned)S);
   if (hook) hook->begin(s);
   if (vec)
-    hipLaunchKernelGGL((kmv_partial_kernel<C, true>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part);
+    hipLaunchKernelGGL((kmv_partial_kernel<C, true>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part, gate);
   else
-    hipLaunchKernelGGL((kmv_partial_kernel<C, false>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part);
+    hipLaunchKernelGGL((kmv_partial_kernel<C, false>), grid, dim3(PC_TPB), 0, s, K, n, ldk, P, rows, part, gate);
   if (hook) hook->end(s);
   hipLaunchKernelGGL((kmv_reduce_kernel<C>), dim3((unsigned)((n + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0, s, part,
-                     S, n, P, lam, Q, pq_part);
+                     S, n, P, lam, Q, pq_part, gate);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -406,25 +499,18 @@ struct PcgState {
   double* relres;  // ||r|| / ||y|| at the column's last update
   int* active;     // 1 while the column iterates
   int* iters;      // updates taken
+  int* any;        // 1 while some column iterates (the gate of every iteration kernel)
 };
 
-__device__ inline double pc_sum_parts(const double* __restrict__ part, int nb, int C, int c) {
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * C + c];
-  return s;
-}
-
-// Fixed-order block sum of one value per thread, written to out (thread 0).
-__device__ inline void pc_block_sum_store(double v, double* out) {
-  __shared__ double red[PC_TPB];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = PC_TPB / 2; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+// st.any = OR of st.active[0..C) (after a barrier that follows the last
+// write of st.active)
+template <int C>
+__device__ inline void pc_store_any(const PcgState& st) {
+  if (threadIdx.x == 0) {
+    int a = 0;
+    for (int c = 0; c < C; ++c) a |= st.active[c];
+    *st.any = a;
   }
-  if (threadIdx.x == 0) *out = red[0];
-  __syncthreads();
 }
 
 // R = Y[:, c0:c0+C], X = 0; partials of ||y||^2.
@@ -444,85 +530,129 @@ __global__ __launch_bounds__(PC_TPB) void pcg_init_kernel(const double* __restri
       X[i * C + c] = 0.0;
     }
   }
-  for (int c = 0; c < C; ++c) pc_block_sum_store(y[c] * y[c], &yy_part[(int64_t)blockIdx.x * C + c]);
+  __shared__ double red[PC_TPB * C];
+  double yy[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) yy[c] = y[c] * y[c];
+  pc_block_sums<C>(yy, red, yy_part + (int64_t)blockIdx.x * C);
 }
 
 template <int C>
-__global__ __launch_bounds__(64) void pcg_init_state_kernel(const double* __restrict__ yy_part, int nb, PcgState st) {
+__global__ __launch_bounds__(PC_TPB) void pcg_init_state_kernel(const double* __restrict__ yy_part, int nb,
+                                                                PcgState st) {
+  __shared__ double red[PC_TPB * C];
+  __shared__ double sum[C];
+  pc_colsum<C>(yy_part, nb, red, sum);
   const int c = threadIdx.x;
-  if (c >= C) return;
-  const double yn = sqrt(pc_sum_parts(yy_part, nb, C, c));
-  st.ynorm[c] = yn;
-  st.active[c] = yn > 0.0 ? 1 : 0;
-  st.iters[c] = 0;
-  st.relres[c] = yn > 0.0 ? 1.0 : 0.0;
-  st.beta[c] = 0.0;
+  if (c < C) {
+    const double yn = sqrt(sum[c]);
+    st.ynorm[c] = yn;
+    st.active[c] = yn > 0.0 ? 1 : 0;
+    st.iters[c] = 0;
+    st.relres[c] = yn > 0.0 ? 1.0 : 0.0;
+    st.beta[c] = 0.0;
+  }
+  __syncthreads();
+  pc_store_any<C>(st);
 }
 
-// W partial: wpart[s][a][c] = sum_{i in split s} Ur[i][a] V[i][c]  (one wave per block)
+// W partial: wpart[s][a][c] = sum_{i in split s} Ur[i][a] V[i][c].  A
+// workgroup takes 64 columns a (lanes) of one row split; its four waves take
+// every fourth row of the split (eight rows in flight each) and add in LDS.
 template <int C>
-__global__ __launch_bounds__(64) void pc_lt_kernel(const double* __restrict__ Ur, int64_t n, int r,
-                                                   const double* __restrict__ V, int64_t rows_per_split,
-                                                   double* __restrict__ wpart) {
-  const int a = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(PC_TPB) void pc_lt_kernel(const double* __restrict__ Ur, int64_t n, int r,
+                                                       const double* __restrict__ V, int64_t rows_per_split,
+                                                       double* __restrict__ wpart, const int* __restrict__ gate) {
+  NK_PCG_GATE(gate)
+  __shared__ double red[3][64][C];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int a = blockIdx.x * 64 + lane;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_split;
   const int64_t i1 = i0 + rows_per_split < n ? i0 + rows_per_split : n;
   double acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0;
   if (a < r) {
-    for (int64_t i = i0; i < i1; ++i) {
+#pragma unroll 8
+    for (int64_t i = i0 + wv; i < i1; i += 4) {
       const double l = Ur[i * r + a];
       const double* vr = V + i * C;
 #pragma unroll
       for (int c = 0; c < C; ++c) acc[c] = fma(l, vr[c], acc[c]);
     }
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[wv - 1][lane][c] = acc[c];
+  }
+  __syncthreads();
+  if (wv == 0 && a < r) {
     double* o = wpart + ((int64_t)blockIdx.y * r + a) * C;
 #pragma unroll
-    for (int c = 0; c < C; ++c) o[c] = acc[c];
+    for (int c = 0; c < C; ++c) o[c] = ((acc[c] + red[0][lane][c]) + red[1][lane][c]) + red[2][lane][c];
   }
 }
 
 // W[a][c] = sum_s wpart[s][a][c]
 template <int C>
 __global__ __launch_bounds__(PC_TPB) void pc_w_reduce_kernel(const double* __restrict__ wpart, int S, int r,
-                                                             double* __restrict__ W) {
+                                                             double* __restrict__ W, const int* __restrict__ gate) {
+  NK_PCG_GATE(gate)
   const int e = blockIdx.x * PC_TPB + threadIdx.x;
   if (e >= r * C) return;
   double s = 0.0;
+#pragma unroll 8
   for (int q = 0; q < S; ++q) s += wpart[(int64_t)q * r * C + e];
   W[e] = s;
 }
+
+// Rows of the preconditioned vector per workgroup of pc_z_kernel (its four
+// waves take a quarter of the rank each and add in LDS).
+constexpr int PC_ZROWS = 64;
 
 // Z[i] = (V[i] - sum_a U[a][i] W[a]) / lam; partials of v.z per column.
 template <int C>
 __global__ __launch_bounds__(PC_TPB) void pc_z_kernel(const double* __restrict__ U, int64_t n, int r,
                                                       const double* __restrict__ W, const double* __restrict__ V,
                                                       double lam, double* __restrict__ Z,
-                                                      double* __restrict__ vz_part) {
-  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
+                                                      double* __restrict__ vz_part, const int* __restrict__ gate) {
+  NK_PCG_GATE(gate)
+  __shared__ double red[4][PC_ZROWS][C];  // wave partials, then the block sums (PC_TPB x C)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * PC_ZROWS + lane;
+  const int a0 = (int)((int64_t)r * wv / 4), a1 = (int)((int64_t)r * (wv + 1) / 4);
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
+  if (i < n) {
+#pragma unroll 4
+    for (int a = a0; a < a1; ++a) {
+      const double l = U[(int64_t)a * n + i];
+      const double* w = W + (int64_t)a * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fma(l, w[c], acc[c]);
+    }
+  }
+  if (wv > 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[wv - 1][lane][c] = acc[c];
+  }
+  __syncthreads();
   double d[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) d[c] = 0.0;
-  if (i < n) {
-    double acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.0;
-    for (int a = 0; a < r; ++a) {
-      const double l = U[(int64_t)a * n + i];
-      const double* z = W + (int64_t)a * C;
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = fma(l, z[c], acc[c]);
-    }
+  if (wv == 0 && i < n) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+      const double t = ((acc[c] + red[0][lane][c]) + red[1][lane][c]) + red[2][lane][c];
       const double v = V[i * C + c];
-      const double z = (v - acc[c]) / lam;
+      const double z = (v - t) / lam;
       Z[i * C + c] = z;
       d[c] = v * z;
     }
   }
-  for (int c = 0; c < C; ++c) pc_block_sum_store(d[c], &vz_part[(int64_t)blockIdx.x * C + c]);
+  __syncthreads();
+  pc_block_sums<C>(d, &red[0][0][0], vz_part + (int64_t)blockIdx.x * C);
 }
 
 // alpha = gamma / p.q for active columns (0 otherwise); X += alpha P,
@@ -532,10 +662,13 @@ __global__ __launch_bounds__(PC_TPB) void pcg_update_kernel(int64_t n, const dou
                                                             PcgState st, const double* __restrict__ P,
                                                             const double* __restrict__ Q, double* __restrict__ X,
                                                             double* __restrict__ R, double* __restrict__ rr_part) {
+  NK_PCG_GATE(st.any)
+  __shared__ double red[PC_TPB * C];
   __shared__ double alpha[C];
+  pc_colsum<C>(pq_part, nb, red, alpha);
   if (threadIdx.x < C) {
     const int c = threadIdx.x;
-    alpha[c] = st.active[c] ? st.gamma[c] / pc_sum_parts(pq_part, nb, C, c) : 0.0;
+    alpha[c] = st.active[c] ? st.gamma[c] / alpha[c] : 0.0;
   }
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
@@ -552,29 +685,41 @@ __global__ __launch_bounds__(PC_TPB) void pcg_update_kernel(int64_t n, const dou
       rr[c] = rv * rv;
     }
   }
-  for (int c = 0; c < C; ++c) pc_block_sum_store(rr[c], &rr_part[(int64_t)blockIdx.x * C + c]);
+  pc_block_sums<C>(rr, red, rr_part + (int64_t)blockIdx.x * C);
 }
 
-// After the update of iteration `it`: residuals, stopping test, counts.
+// After the update of iteration `it`: residuals, stopping test, counts, and
+// the gate for the rest of the pass.
 template <int C>
-__global__ __launch_bounds__(64) void pcg_residual_kernel(const double* __restrict__ rr_part, int nb, PcgState st,
-                                                          int it, double tol) {
+__global__ __launch_bounds__(PC_TPB) void pcg_residual_kernel(const double* __restrict__ rr_part, int nb,
+                                                              PcgState st, int it, double tol) {
+  NK_PCG_GATE(st.any)
+  __shared__ double red[PC_TPB * C];
+  __shared__ double sum[C];
+  pc_colsum<C>(rr_part, nb, red, sum);
   const int c = threadIdx.x;
-  if (c >= C || !st.active[c]) return;
-  const double rel = sqrt(pc_sum_parts(rr_part, nb, C, c)) / st.ynorm[c];
-  st.relres[c] = rel;
-  st.iters[c] = it + 1;
-  if (rel <= tol) st.active[c] = 0;
+  if (c < C && st.active[c]) {
+    const double rel = sqrt(sum[c]) / st.ynorm[c];
+    st.relres[c] = rel;
+    st.iters[c] = it + 1;
+    if (rel <= tol) st.active[c] = 0;
+  }
+  __syncthreads();
+  pc_store_any<C>(st);
 }
 
 // gamma' = r.z; beta = gamma'/gamma for active columns (0 otherwise);
 // gamma <- gamma' for active columns.  first: gamma <- gamma' only.
 template <int C>
-__global__ __launch_bounds__(64) void pcg_beta_kernel(const double* __restrict__ rz_part, int nb, PcgState st,
-                                                      int first) {
+__global__ __launch_bounds__(PC_TPB) void pcg_beta_kernel(const double* __restrict__ rz_part, int nb, PcgState st,
+                                                          int first) {
+  NK_PCG_GATE(st.any)
+  __shared__ double red[PC_TPB * C];
+  __shared__ double sum[C];
+  pc_colsum<C>(rz_part, nb, red, sum);
   const int c = threadIdx.x;
   if (c >= C) return;
-  const double g = pc_sum_parts(rz_part, nb, C, c);
+  const double g = sum[c];
   if (first) {
     st.gamma[c] = g;
     st.beta[c] = 0.0;
@@ -589,6 +734,7 @@ __global__ __launch_bounds__(64) void pcg_beta_kernel(const double* __restrict__
 template <int C>
 __global__ __launch_bounds__(PC_TPB) void pcg_direction_kernel(int64_t n, PcgState st, const double* __restrict__ Z,
                                                                double* __restrict__ P, int first) {
+  NK_PCG_GATE(st.any)
   const int64_t e = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
   if (e >= n * C) return;
   const int c = (int)(e % C);
@@ -606,55 +752,68 @@ __global__ __launch_bounds__(PC_TPB) void pcg_store_kernel(int64_t n, const doub
   X[i * ldx + c0 + c] = Xg[e];
 }
 
-// One CG pass over a group of C <= 16 right-hand-side columns.
+// One CG pass over a group of C <= 16 right-hand-side columns.  The host
+// enqueues iterations ahead of the device and reads the gate of iteration
+// it - 2 (copied to pinned host memory behind an event) before enqueueing
+// iteration it, so the device never waits for the host; iterations
+// enqueued after every column stopped return at once.
 template <int C>
 int pcg_group(const PcgArgs& a, int64_t c0, hipStream_t s) {
   const int64_t n = a.n;
   const int nb = (int)((n + PC_TPB - 1) / PC_TPB);
+  const int nbz = (int)((n + PC_ZROWS - 1) / PC_ZROWS);
   const unsigned gv = (unsigned)((n * C + PC_TPB - 1) / PC_TPB);
-  PcgState st{a.gamma, a.beta, a.ynorm, a.relres, a.active, a.iters};
-  // r-side split of L^T v
+  PcgState st{a.gamma, a.beta, a.ynorm, a.relres, a.active, a.iters, a.any};
   const int lt_splits = a.lt_splits;
   const int64_t lt_rows = (n + lt_splits - 1) / lt_splits;
 
   auto precond = [&](const double* V, double* Z, double* vz_part) {
     if (a.r > 0) {
-      hipLaunchKernelGGL((pc_lt_kernel<C>), dim3((unsigned)((a.r + 63) / 64), (unsigned)lt_splits), dim3(64), 0, s,
-                         a.Ur, n, a.r, V, lt_rows, a.wpart);
+      hipLaunchKernelGGL((pc_lt_kernel<C>), dim3((unsigned)((a.r + 63) / 64), (unsigned)lt_splits), dim3(PC_TPB), 0, s,
+                         a.Ur, n, a.r, V, lt_rows, a.wpart, a.any);
       hipLaunchKernelGGL((pc_w_reduce_kernel<C>), dim3((unsigned)((a.r * C + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0,
-                         s, a.wpart, lt_splits, a.r, a.W);
+                         s, a.wpart, lt_splits, a.r, a.W, a.any);
     }
-    hipLaunchKernelGGL((pc_z_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, a.U, n, a.r, a.W, V, a.lam, Z, vz_part);
+    hipLaunchKernelGGL((pc_z_kernel<C>), dim3(nbz), dim3(PC_TPB), 0, s, a.U, n, a.r, a.W, V, a.lam, Z, vz_part,
+                       a.any);
   };
 
   hipLaunchKernelGGL((pcg_init_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, a.Y, a.ldy, c0, n, a.R, a.X, a.part1);
-  hipLaunchKernelGGL((pcg_init_state_kernel<C>), dim3(1), dim3(64), 0, s, a.part1, nb, st);
+  hipLaunchKernelGGL((pcg_init_state_kernel<C>), dim3(1), dim3(PC_TPB), 0, s, a.part1, nb, st);
   precond(a.R, a.Z, a.part2);
-  hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(64), 0, s, a.part2, nb, st, 1);
+  hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(PC_TPB), 0, s, a.part2, nbz, st, 1);
   hipLaunchKernelGGL((pcg_direction_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, st, a.Z, a.P, 1);
   if (hipGetLastError() != hipSuccess) return -3;
 
-  int done_iters = 0;
-  for (int it = 0; it < a.max_iter; ++it) {
-    if (it > 0 && it % a.check_every == 0) {
-      int act[16];
-      if (hipMemcpyAsync(act, a.active, sizeof(int) * C, hipMemcpyDeviceToHost, s) != hipSuccess) return -3;
-      if (hipStreamSynchronize(s) != hipSuccess) return -3;
-      bool any = false;
-      for (int c = 0; c < C; ++c) any = any || act[c] != 0;
-      if (!any) break;
+  int rc = 0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (int e = 0; e < 3 && rc == 0; ++e)
+    if (hipEventCreateWithFlags(&ev[e], hipEventDisableTiming) != hipSuccess) rc = -3;
+  for (int it = 0; it < a.max_iter && rc == 0; ++it) {
+    if (it >= 2) {
+      if (hipEventSynchronize(ev[(it - 2) % 3]) != hipSuccess) {
+        rc = -3;
+        break;
+      }
+      if (a.host_any[(it - 2) % 3] == 0) break;
     }
-    if (launch_kmv_c<C>(a.K, n, a.ldk, a.P, a.lam, a.kpart, a.Q, a.part1, s, a.hook)) return -3;
+    if (launch_kmv_c<C>(a.K, n, a.ldk, a.P, a.lam, a.kpart, a.Q, a.part1, a.any, s, a.hook)) {
+      rc = -3;
+      break;
+    }
     hipLaunchKernelGGL((pcg_update_kernel<C>), dim3(nb), dim3(PC_TPB), 0, s, n, a.part1, nb, st, a.P, a.Q, a.X, a.R,
                        a.part2);
-    hipLaunchKernelGGL((pcg_residual_kernel<C>), dim3(1), dim3(64), 0, s, a.part2, nb, st, it, a.tol);
+    hipLaunchKernelGGL((pcg_residual_kernel<C>), dim3(1), dim3(PC_TPB), 0, s, a.part2, nb, st, it, a.tol);
     precond(a.R, a.Z, a.part1);
-    hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(64), 0, s, a.part1, nb, st, 0);
+    hipLaunchKernelGGL((pcg_beta_kernel<C>), dim3(1), dim3(PC_TPB), 0, s, a.part1, nbz, st, 0);
     hipLaunchKernelGGL((pcg_direction_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, st, a.Z, a.P, 0);
-    if (hipGetLastError() != hipSuccess) return -3;
-    done_iters = it + 1;
+    if (hipMemcpyAsync(&a.host_any[it % 3], a.any, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ev[it % 3], s) != hipSuccess || hipGetLastError() != hipSuccess)
+      rc = -3;
   }
-  (void)done_iters;
+  for (int e = 0; e < 3; ++e)
+    if (ev[e]) (void)hipEventDestroy(ev[e]);
+  if (rc) return rc;
   hipLaunchKernelGGL((pcg_store_kernel<C>), dim3(gv), dim3(PC_TPB), 0, s, n, a.X, a.Xout, a.ldx, c0);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
@@ -686,7 +845,7 @@ int launch_kmv(const float* K, int64_t n, int64_t ldk, const double* P, int C, d
   switch (C) {
 #define NK_KMV_CASE(c) \
   case c:              \
-    return launch_kmv_c<c>(K, n, ldk, P, lam, part, Q, pq_part, s, hook);
+    return launch_kmv_c<c>(K, n, ldk, P, lam, part, Q, pq_part, nullptr, s, hook);
     NK_KMV_CASE(1) NK_KMV_CASE(2) NK_KMV_CASE(3) NK_KMV_CASE(4) NK_KMV_CASE(5) NK_KMV_CASE(6) NK_KMV_CASE(7)
     NK_KMV_CASE(8) NK_KMV_CASE(9) NK_KMV_CASE(10) NK_KMV_CASE(11) NK_KMV_CASE(12) NK_KMV_CASE(13)
     NK_KMV_CASE(14) NK_KMV_CASE(15) NK_KMV_CASE(16)

@@ -105,6 +105,11 @@ WORKLOADS = {
                              seeds=(4001, 4002, 4003), n_tiles=64, lo=32, hi=2048,
                              depth=(2, 2, 2), sigma_w2=2.0, sigma_b2=0.0,
                              big_hw=64, big_n=256, big_length=6.0, big_seeds=(4004, 4005)),
+    # Kernel regression by preconditioned CG: a 32768 x 32768 float32 Gram
+    # (the FC-3 NNGP of 32x32x3 correlated images) and 10 one-hot targets.
+    "fc3_pcg_32768": dict(kind="corr", n=32768, hw=32, c=3, length=3.0, seeds=(6001, 6002),
+                          fc_depth=3, fc_sigma_w2=2.0, fc_sigma_b2=0.01, ridge_rel=1e-4,
+                          n_classes=10, rank=512, tol=1e-8, max_iter=3000, cpu_n=4096),
     # Myrtle-5 KRR distillation: 256 support + 2048 targets at 32x32x3.
     "myrtle5_krr_grad": dict(kind="corr", n_support=256, n_target=2048, hw=32, c=3,
                              length=3.0, seeds=(5001, 5002, 5003, 5004),

@@ -157,6 +157,25 @@ def test_krr_pcg_matches_oracle(nk, tol):
     _check_pcg(k32, y, got, ref, tol, band)
 
 
+def test_krr_pcg_4096_rank64_does_not_stall(nk):
+    """n = 4096, rank 64: the case where a Woodbury matrix M = lam I + L^T L
+    summed naively over the 4096 rows (about 3e-15 relative error instead
+    of about 1e-16) made five of the ten columns stall near 1e-8 for some 50
+    iterations; M is now accumulated with compensated sums."""
+    m = 4096
+    xs = synth.correlated_images(m, 16, 16, 3, 3.0, 77)
+    y = synth.teacher_labels(xs, 10, 78).astype(np.float64)
+    k32 = oracle.fc_nngp(xs.reshape(m, -1), xs.reshape(m, -1)).astype(np.float32)
+    k64 = k32.astype(np.float64)
+    lam = solvers.ridge_lambda(k64, 1e-4, True)
+    _say("pcg n=4096 c=10 rank=64")
+    got = nk.krr_pcg(torch.from_numpy(k32).cuda(), torch.from_numpy(y).cuda(), 1e-4, True, rank=64, tol=1e-8,
+                     max_iter=3000)
+    ref = solvers.pcg(k64, y, lam, 64, 1e-8, 3000)
+    _say(f"  iterations {got[1].tolist()} vs {ref['iters'].tolist()}")
+    _check_pcg(k32, y, got, ref, 1e-8, np.full(10, 3))
+
+
 def test_krr_pcg_two_groups_zero_column_and_plain_cg(nk):
     k32, x = _gram32(600, 35, hw=8)
     rng = np.random.default_rng(36)
