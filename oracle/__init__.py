@@ -13,6 +13,9 @@ Contents
   kernel (the kernel of the paper's large-scale runs) with its NNGP, same C
   file.
 * ``fc_nngp`` -- the FC3 NNGP (App. A, FC listing), same C file.
+* ``cv_self`` / ``cv_pairs`` / ``cv_gram`` -- the CNN-VEC (CV8) NNGP
+  (App. A, CNN-VEC listing: full-resolution convs, Flatten readout), same C
+  file.
 * ``krr_predict`` -- kernel ridge regression, the linear system that the
   paper's conjugate-gradient solver targets (Sec. 2, iterative solvers),
   solved exactly with a float64 Cholesky factorisation.
@@ -74,6 +77,10 @@ def _load():
     lib.nko_relu_dot.restype = cd
     lib.nko_myrtle_ntk_pairs.argtypes = [P, P, P, P, ci, ci, ci, ci, P, cd, cd, P, i64, P, P, ci]
     lib.nko_myrtle_ntk_pairs.restype = ci
+    lib.nko_cv_self.argtypes = [P, i64, ci, ci, ci, ci, cd, cd, P, P, ci]
+    lib.nko_cv_self.restype = ci
+    lib.nko_cv_pairs.argtypes = [P, P, P, P, ci, ci, ci, ci, cd, cd, P, i64, P, ci]
+    lib.nko_cv_pairs.restype = ci
     lib.nko_num_threads.argtypes = []
     lib.nko_num_threads.restype = ci
     _lib = lib
@@ -254,6 +261,55 @@ def fc_nngp(x1: np.ndarray, x2: np.ndarray, depth: int = 3, sigma_w2: float = 2.
     if rc != 0:
         raise ValueError(f"oracle nko_fc_nngp failed ({rc})")
     return K
+
+
+def cv_self(x: np.ndarray, depth: int = 8, sigma_w2: float = 2.0, sigma_b2: float = 0.01,
+            threads: int | None = None):
+    """CNN-VEC variance maps (n, depth, h*w) and self kernels K(x, x) (n,)."""
+    x = _check_images(x)
+    n, h, w, c = x.shape
+    q = np.zeros((n, depth, h * w), dtype=np.float64)
+    k = np.zeros(n, dtype=np.float64)
+    rc = _load().nko_cv_self(_ptr(x), n, h, w, c, depth, sigma_w2, sigma_b2, _ptr(q), _ptr(k),
+                             threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle nko_cv_self failed ({rc})")
+    return q, k
+
+
+def cv_pairs(x1: np.ndarray, x2: np.ndarray, pairs: np.ndarray, depth: int = 8, sigma_w2: float = 2.0,
+             sigma_b2: float = 0.01, q1=None, q2=None, threads: int | None = None) -> np.ndarray:
+    """CNN-VEC NNGP K(x1[a], x2[b]) for each row (a, b) of ``pairs`` (float64)."""
+    x1 = _check_images(x1)
+    x2 = _check_images(x2)
+    n1, h, w, c = x1.shape
+    if x2.shape[1:] != (h, w, c):
+        raise ValueError("image shapes differ")
+    pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+    if pairs.size and (pairs[:, 0].min() < 0 or pairs[:, 0].max() >= n1 or pairs[:, 1].min() < 0
+                       or pairs[:, 1].max() >= x2.shape[0]):
+        raise IndexError("pair index out of range")
+    if q1 is None:
+        q1, _ = cv_self(x1, depth, sigma_w2, sigma_b2, threads)
+    if q2 is None:
+        q2, _ = cv_self(x2, depth, sigma_w2, sigma_b2, threads)
+    q1 = np.ascontiguousarray(q1, dtype=np.float64)
+    q2 = np.ascontiguousarray(q2, dtype=np.float64)
+    out = np.zeros(pairs.shape[0], dtype=np.float64)
+    rc = _load().nko_cv_pairs(_ptr(x1), _ptr(q1), _ptr(x2), _ptr(q2), h, w, c, depth, sigma_w2, sigma_b2,
+                              _ptr(pairs), pairs.shape[0], _ptr(out), threads or default_threads())
+    if rc != 0:
+        raise ValueError(f"oracle nko_cv_pairs failed ({rc})")
+    return out
+
+
+def cv_gram(x1: np.ndarray, x2: np.ndarray | None, depth: int = 8, sigma_w2: float = 2.0, sigma_b2: float = 0.01,
+            threads: int | None = None) -> np.ndarray:
+    """Full CNN-VEC NNGP block (n1, n2), float64."""
+    x2 = x1 if x2 is None else x2
+    a, b = np.meshgrid(np.arange(len(x1)), np.arange(len(x2)), indexing="ij")
+    pairs = np.stack([a.ravel(), b.ravel()], 1)
+    return cv_pairs(x1, x2, pairs, depth, sigma_w2, sigma_b2, threads=threads).reshape(len(x1), len(x2))
 
 
 def krr_ridge(k_train: np.ndarray, ridge_rel: float) -> float:

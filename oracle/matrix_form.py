@@ -84,6 +84,24 @@ def myrtle_pair(x1: np.ndarray, x2: np.ndarray, depth: Sequence[int], sw2: float
     return float(sw2 * M[:n, n:].mean() + sb2)
 
 
+def cv_pair(x1: np.ndarray, x2: np.ndarray, depth: int, sw2: float, sb2: float) -> float:
+    """CNN-VEC NNGP of one pair in the joint-matrix form: ``depth`` conv/ReLU
+    blocks at full resolution, then the Flatten + Dense readout, i.e.
+    sw2 times the mean over pixels i of the cross-block entry (i, i), + sb2."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    h, w, c = x1.shape
+    X = np.concatenate([x1.reshape(h * w, c), x2.reshape(h * w, c)], axis=0)
+    M = X @ X.T / c
+    T = [_blockdiag(_shift(h, w, dy, dx)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    for _ in range(depth):
+        M = sw2 / 9.0 * sum(t @ M @ t.T for t in T) + sb2
+        q = np.diag(M).copy()
+        M = _F(M, q[:, None], q[None, :])
+    n = h * w
+    return float(sw2 * np.mean(np.diag(M[:n, n:])) + sb2)
+
+
 def _Fdot(s, q1, q2):
     """E[relu'(u) relu'(v)] = (pi - t) / (2 pi), entry-wise."""
     qq = q1 * q2

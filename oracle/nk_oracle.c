@@ -497,6 +497,118 @@ int nko_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, int d,
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* CNN-VEC (App. "Neural Kernel Architecture", CNN-VEC listing)              */
+/* ------------------------------------------------------------------------ */
+/*
+ * depth blocks of [3x3 SAME conv, ReLU] at full resolution, Flatten, Dense.
+ * The flatten readout averages the covariance of each pixel of x with the
+ * SAME pixel of x': K = sw2 mean_i A(i, i) + sb2.  A conv only couples
+ * (i, j) to (i + d, j + d), so the entries (i, i) form a closed recursion
+ * over one h x w map per pair:
+ *   S(i) = x(i).x'(i) / C,
+ *   per block: V(i) = sw2 / 9 sum_{|d| <= 1, i + d inside} S(i + d) + sb2,
+ *              S(i) = F(V(i), q_x(i), q_x'(i)),
+ * with q_x the same recursion run on the pair (x, x) (whose V is its own
+ * variance map).
+ */
+
+/* one block: V = conv of S (zero padding, /9 always), then S = F(V, q1, q2) */
+static void cv_block(double* S, double* V, int h, int w, double sw2, double sb2) {
+  for (int iy = 0; iy < h; ++iy)
+    for (int ix = 0; ix < w; ++ix) {
+      double s = 0.0;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int y = iy + dy, x = ix + dx;
+          if (y < 0 || y >= h || x < 0 || x >= w) continue;
+          s += S[(size_t)y * w + x];
+        }
+      V[(size_t)iy * w + ix] = sw2 / 9.0 * s + sb2;
+    }
+}
+
+static void cv_seed(const float* x1, const float* x2, int hw, int c, double* S) {
+  for (int i = 0; i < hw; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < c; ++k) s += (double)x1[(size_t)i * c + k] * (double)x2[(size_t)i * c + k];
+    S[i] = s / c;
+  }
+}
+
+/* Variance maps q[img][block][pixel] (the pre-activation variance at each
+ * ReLU) and K(x, x) of each image. */
+int nko_cv_self(const float* x, int64_t n, int H, int W, int C, int depth, double sw2, double sb2, double* q,
+                double* kdiag, int nthreads) {
+  if (n < 0 || H <= 0 || W <= 0 || C <= 0 || depth < 1 || !(sw2 > 0.0) || sb2 < 0.0) return -1;
+  const int hw = H * W;
+  int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+  {
+    double* S = (double*)malloc(sizeof(double) * hw);
+    double* V = (double*)malloc(sizeof(double) * hw);
+    if (!S || !V) {
+#pragma omp atomic write
+      err = -4;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t a = 0; a < n; ++a) {
+        const float* xa = x + (size_t)a * hw * C;
+        cv_seed(xa, xa, hw, C, S);
+        for (int l = 0; l < depth; ++l) {
+          cv_block(S, V, H, W, sw2, sb2);
+          double* qa = q + ((size_t)a * depth + l) * hw;
+          for (int i = 0; i < hw; ++i) {
+            qa[i] = V[i];
+            S[i] = relu_map(V[i], V[i], V[i]);
+          }
+        }
+        double m = 0.0;
+        for (int i = 0; i < hw; ++i) m += S[i];
+        kdiag[a] = sw2 * m / hw + sb2;
+      }
+    }
+    free(S);
+    free(V);
+  }
+  return err;
+}
+
+/* K(x1[a], x2[b]) for each listed pair, given both images' variance maps. */
+int nko_cv_pairs(const float* x1, const double* q1, const float* x2, const double* q2, int H, int W, int C,
+                 int depth, double sw2, double sb2, const int64_t* pairs, int64_t np, double* out, int nthreads) {
+  if (H <= 0 || W <= 0 || C <= 0 || depth < 1 || !(sw2 > 0.0) || sb2 < 0.0 || np < 0) return -1;
+  const int hw = H * W;
+  int err = 0;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+  {
+    double* S = (double*)malloc(sizeof(double) * hw);
+    double* V = (double*)malloc(sizeof(double) * hw);
+    if (!S || !V) {
+#pragma omp atomic write
+      err = -4;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t p = 0; p < np; ++p) {
+        const int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
+        cv_seed(x1 + (size_t)a * hw * C, x2 + (size_t)b * hw * C, hw, C, S);
+        for (int l = 0; l < depth; ++l) {
+          cv_block(S, V, H, W, sw2, sb2);
+          const double* qa = q1 + ((size_t)a * depth + l) * hw;
+          const double* qb = q2 + ((size_t)b * depth + l) * hw;
+          for (int i = 0; i < hw; ++i) S[i] = relu_map(V[i], qa[i], qb[i]);
+        }
+        double m = 0.0;
+        for (int i = 0; i < hw; ++i) m += S[i];
+        out[p] = sw2 * m / hw + sb2;
+      }
+    }
+    free(S);
+    free(V);
+  }
+  return err;
+}
+
 /* The ReLU map itself, exposed for the quadrature pin. */
 double nko_relu_map(double s, double q1, double q2) { return relu_map(s, q1, q2); }
 

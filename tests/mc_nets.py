@@ -84,3 +84,20 @@ def myrtle_empirical_ntk(x: np.ndarray, depth, sw2: float, sb2: float, width: in
                                 for t, p in zip(gr, allp)]))
     G = torch.stack(grads)
     return (G @ G.T).numpy()
+
+
+def cv_empirical(x: np.ndarray, depth: int, sw2: float, sb2: float, width: int, seed: int) -> np.ndarray:
+    """Empirical NNGP of a random CNN-VEC network: ``depth`` SAME 3x3 conv + ReLU
+    layers at full resolution (weights N(0, sw2 / (9 C_in)), biases N(0, sb2)),
+    Flatten, and a Dense readout whose randomness is integrated out:
+    sw2 <f, f'> / (h w width) + sb2."""
+    g = torch.Generator().manual_seed(seed)
+    h = torch.tensor(np.asarray(x, dtype=np.float32)).permute(0, 3, 1, 2).contiguous()
+    cin = h.shape[1]
+    for _ in range(depth):
+        w = torch.randn(width, cin, 3, 3, generator=g) * math.sqrt(sw2 / (9 * cin))
+        b = torch.randn(width, generator=g) * math.sqrt(sb2)
+        h = torch.relu(torch.nn.functional.conv2d(h, w, b, padding=1))
+        cin = width
+    f = h.reshape(h.shape[0], -1).double()
+    return (sw2 * f @ f.T / f.shape[1] + sb2).numpy()
