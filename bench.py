@@ -44,6 +44,7 @@ def _args():
     p.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain tile comparison")
     p.add_argument("--no-ntk", action="store_true", help="skip the Myrtle-10 NTK measurement")
     p.add_argument("--no-pcg", action="store_true", help="skip the preconditioned-CG solve measurement")
+    p.add_argument("--no-cv8", action="store_true", help="skip the CV8 NNGP measurement")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -180,6 +181,61 @@ def _batched(torch, full: bool):
             "pairs": pairs, "batched_pairs_per_s": round(pairs / res["batched"], 1),
             "plain_pairs_per_s": round(pairs / res["plain"], 1), "speedup": round(res["plain"] / res["batched"], 4),
             "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands)}
+
+
+def _cv8(torch, cpu: bool):
+    """CV8 NNGP (CNN-VEC, depth 8, flatten readout) on one 4096 x 4096 block of
+    32x32x3 images: one untimed and one timed call, the pair kernel's ALU
+    roofline, and the FP64 oracle on a 64 x 64 sub-block with its parity."""
+    import numpy as np
+
+    import synth
+    from paper_2303_05420_amd import _lib, ops, workmodel
+
+    w = synth.WORKLOADS["cv8_32x32_4096"]
+    n, hw, depth = w["n1"], w["hw"], w["depth"]
+    xa = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][0])
+    xb = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][1])
+    ta, tb = torch.from_numpy(xa).cuda(), torch.from_numpy(xb).cuda()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ops.cv_nngp(ta, tb, depth, w["sigma_w2"], w["sigma_b2"], out=out)
+    torch.cuda.synchronize()
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    ops.cv_nngp(ta, tb, depth, w["sigma_w2"], w["sigma_b2"], out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    kern = f"cv_pairs_n{hw}"
+    launches, kms = prof[kern]
+    flops = workmodel.cv_flops_per_pair(hw, 3, depth) * n * n
+    achieved = flops / (kms / launches / 1e3) / 1e12
+    res = {"workload": f"CV8 NNGP (CNN-VEC depth 8, flatten readout), 32x32x3 correlated images, one {n}x{n} block",
+           "value": round(n * n / dt, 1), "unit": "entries/s", "ms": round(dt * 1e3, 3),
+           "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": kern, "avg_launch_ms": round(kms / launches, 3)}}
+    print(f"cv8: {dt * 1e3:.1f} ms for {n * n} entries", file=sys.stderr, flush=True)
+    if cpu:
+        import oracle
+
+        m = 64
+        t0 = time.perf_counter()
+        q1, d1 = oracle.cv_self(xa[:m], depth, w["sigma_w2"], w["sigma_b2"])
+        q2, d2 = oracle.cv_self(xb[:m], depth, w["sigma_w2"], w["sigma_b2"])
+        a, b = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+        ref = oracle.cv_pairs(xa[:m], xb[:m], np.stack([a.ravel(), b.ravel()], 1), depth, w["sigma_w2"],
+                              w["sigma_b2"], q1, q2).reshape(m, m)
+        cdt = time.perf_counter() - t0
+        err = float(np.max(np.abs(out[:m, :m].cpu().numpy() - ref) / np.sqrt(np.outer(d1, d2))))
+        res["cpu_baseline"] = {"value": round(m * m / cdt, 1), "unit": "entries/s", "kind": "oracle",
+                               "cores": min(16, len(os.sched_getaffinity(0))),
+                               "sample": f"{m}x{m} sub-block of the same block plus its {2 * m} self recursions"}
+        res["parity"] = {"max_normalised_error": err, "entries": m * m, "tolerance": 2e-5}
+    return res
 
 
 def _pcg(torch, cpu: bool):
@@ -365,6 +421,7 @@ def main():
     batched = None if a.no_batched else _batched(torch, a.batched_full)
     ntk = None if a.no_ntk else _ntk(torch)
     pcg = None if a.no_pcg else _pcg(torch, not a.no_cpu_baseline)
+    cv8 = None if a.no_cv8 else _cv8(torch, not a.no_cpu_baseline)
 
     cpu = None
     parity = None
@@ -414,6 +471,7 @@ def main():
         "batched_tiles": batched,
         "ntk": ntk,
         "pcg": pcg,
+        "cv8": cv8,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))

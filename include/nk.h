@@ -63,7 +63,8 @@ enum {
   NK_OP_MYRTLE_NTK = 5,
   NK_OP_PCG = 6,          /* cfg: nk_pcg_cfg; n1 = n, n2 = c */
   NK_OP_PIVOTED_CHOL = 7, /* cfg: NULL; n1 = n, n2 = rank */
-  NK_OP_GRAM_MATVEC = 8   /* cfg: NULL; n1 = n, n2 = c */
+  NK_OP_GRAM_MATVEC = 8,  /* cfg: NULL; n1 = n, n2 = c */
+  NK_OP_CV = 9            /* cfg: nk_cv_cfg; n1, n2 = block sizes (n2 = 0 for a symmetric block) */
 };
 
 /*
@@ -246,6 +247,31 @@ typedef struct {
  * for this configuration in this process. */
 int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
                              nk_batched_candidate* chosen);
+
+/*
+ * CNN-VEC network (App. "Neural Kernel Architecture", CNN-VEC listing; CV8 =
+ * depth 8): `depth` blocks of [3x3 SAME conv, ReLU] at full resolution
+ * H x W, Flatten, Dense readout; conv weight variance sigma_w2 / (9 C_in),
+ * biases sigma_b2, readout weight variance sigma_w2 / (H W C_in).
+ * Supported: H == W a power of two with 2 <= H <= 32, 1 <= C <= 4,
+ * 1 <= depth <= 16, sigma_w2 > 0, sigma_b2 >= 0.
+ */
+typedef struct {
+  int32_t H, W, C, depth;
+  float sigma_w2, sigma_b2;
+} nk_cv_cfg;
+
+/*
+ * CNN-VEC NNGP block: K[a * ldk + b] = k_CV(x1[a], x2[b]).  The flatten
+ * readout averages the covariance of each pixel with the same pixel of the
+ * other image, so only those n^2 entries per pair are propagated.  x1, x2:
+ * NHWC float32 device images; K float32 device, row-major, ldk >= n2.
+ * x1 == x2 && n1 == n2 selects the symmetric path (upper triangle computed,
+ * mirrored).  Workspace: nk_workspace_size(NK_OP_CV, cfg, n1, n2) (pass n2
+ * = 0 for a symmetric block).  Asynchronous on `stream`.
+ */
+int nk_cv_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_cv_cfg* cfg, float* K,
+               int64_t ldk, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Partial pivoted Cholesky factor of a symmetric positive semi-definite

@@ -27,6 +27,7 @@ NK_OP_MYRTLE_NTK = 5
 NK_OP_PCG = 6
 NK_OP_PIVOTED_CHOL = 7
 NK_OP_GRAM_MATVEC = 8
+NK_OP_CV = 9
 
 
 class MyrtleCfg(ctypes.Structure):
@@ -48,6 +49,11 @@ class Tile(ctypes.Structure):
 class BatchedCandidate(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int64), ("pair_tile", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("us_per_pair", ctypes.c_double)]
+
+
+class CvCfg(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("sigma_w2", ctypes.c_float), ("sigma_b2", ctypes.c_float)]
 
 
 class PcgCfg(ctypes.Structure):
@@ -108,6 +114,8 @@ def lib():
                                            ctypes.POINTER(BatchedCandidate)]
     L.nk_myrtle_batched_tuning.restype = ci
     dbl = ctypes.c_double
+    L.nk_cv_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(CvCfg), P, i64, P, sz, P]
+    L.nk_cv_nngp.restype = ci
     L.nk_pivoted_cholesky.argtypes = [P, i64, i64, i32, dbl, P, P, ctypes.POINTER(i32), P, sz, P]
     L.nk_pivoted_cholesky.restype = ci
     L.nk_gram_matvec.argtypes = [P, i64, i64, P, i64, dbl, P, P, sz, P]

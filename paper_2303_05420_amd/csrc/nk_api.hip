@@ -554,6 +554,39 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
 }
 
 
+// ---- CNN-VEC ---------------------------------------------------------------
+
+constexpr int kCvMaxDepth = 16;
+
+int check_cv(const nk_cv_cfg* c) {
+  if (!c) return fail(NK_EINVAL, "cfg is NULL");
+  if (c->H <= 0 || c->W <= 0 || c->C <= 0 || c->depth <= 0) return fail(NK_EINVAL, "H, W, C, depth must be positive");
+  if (!(c->sigma_w2 > 0.f) || !(c->sigma_b2 >= 0.f)) return fail(NK_EINVAL, "need sigma_w2 > 0 and sigma_b2 >= 0");
+  if (c->H != c->W || !is_pow2(c->H) || c->H < 2 || c->H > 32)
+    return fail(NK_EUNSUPPORTED, "need H == W a power of two in [2, 32]");
+  if (c->C > 4) return fail(NK_EUNSUPPORTED, "C > 4");
+  if (c->depth > kCvMaxDepth) return fail(NK_EUNSUPPORTED, "depth > %d", kCvMaxDepth);
+  return 0;
+}
+
+struct CvPlan {
+  size_t tab1, tab2, d1, d2, total;
+};
+
+CvPlan cv_plan(const nk_cv_cfg* c, int64_t n1, int64_t n2, bool sym) {
+  CvPlan p{};
+  Bump b;
+  const size_t per = (size_t)c->depth * c->H * c->W * sizeof(float2);
+  p.tab1 = b.take(per * (size_t)std::max<int64_t>(n1, 1));
+  p.d1 = b.take(sizeof(float) * (size_t)std::max<int64_t>(n1, 1));
+  if (!sym) {
+    p.tab2 = b.take(per * (size_t)std::max<int64_t>(n2, 1));
+    p.d2 = b.take(sizeof(float) * (size_t)std::max<int64_t>(n2, 1));
+  }
+  p.total = b.off + 256;
+  return p;
+}
+
 // ---- kernel regression by preconditioned conjugate gradients --------------
 
 constexpr int kPcgMaxRank = 8192;  // LDS of a pivot step holds one row of L
@@ -726,6 +759,11 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
     case NK_OP_GRAM_MATVEC:
       if (n1 <= 0) return 0;
       return pcg_plan(n1, 0, 2).total;
+    case NK_OP_CV: {
+      const nk_cv_cfg* c = static_cast<const nk_cv_cfg*>(cfg);
+      if (check_cv(c) || n1 <= 0 || n2 < 0) return 0;
+      return cv_plan(c, n1, n2, n2 == 0).total;
+    }
     default:
       return 0;
   }
@@ -1017,6 +1055,39 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
   return ok();
 }
 
+
+int nk_cv_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_cv_cfg* cfg, float* K,
+               int64_t ldk, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_cv(cfg);
+  if (rc) return rc;
+  if (!x1 || !x2 || !K) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0) return fail(NK_EINVAL, "n1 and n2 must be positive");
+  if (ldk < n2) return fail(NK_EINVAL, "ldk < n2");
+  const bool sym = (x1 == x2) && (n1 == n2);
+  const CvPlan cp = cv_plan(cfg, n1, n2, sym);
+  if (!ws || ws_bytes < cp.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", cp.total);
+  hipStream_t s = (hipStream_t)stream;
+  const int N = cfg->H;
+  float2* t1 = at<float2>(ws, cp.tab1);
+  float2* t2 = sym ? t1 : at<float2>(ws, cp.tab2);
+  {
+    ProfScope ps("cv_prepare", s);
+    if (nk::launch_cv_prepare(x1, n1, N, cfg->C, cfg->depth, cfg->sigma_w2, cfg->sigma_b2, t1,
+                              at<float>(ws, cp.d1), s))
+      return hip_fail("cv prepare");
+    if (!sym && nk::launch_cv_prepare(x2, n2, N, cfg->C, cfg->depth, cfg->sigma_w2, cfg->sigma_b2, t2,
+                                      at<float>(ws, cp.d2), s))
+      return hip_fail("cv prepare");
+  }
+  const float seed_scale = (float)((double)cfg->sigma_w2 / (9.0 * cfg->C));
+  char nm[32];
+  snprintf(nm, sizeof nm, "cv_pairs_n%d", N);
+  ProfScope ps(nm, s);
+  if (nk::launch_cv_pairs(N, x1, x2, n1, n2, sym ? 1 : 0, kPairTile, cfg->C, cfg->depth, t1, t2, K, ldk,
+                          cfg->sigma_b2, seed_scale, s))
+    return hip_fail("cv pairs");
+  return ok();
+}
 
 int nk_pivoted_cholesky(const float* K, int64_t n, int64_t ldk, int32_t rank, double pivot_tol, double* L,
                         int32_t* piv, int32_t* rank_used, void* ws, size_t ws_bytes, void* stream) {

@@ -180,4 +180,12 @@ int launch_kmv(const float* K, int64_t n, int64_t ldk, const double* P, int C, d
                double* pq_part, hipStream_t s, ProfHook* hook);
 int launch_diag_mean(const float* K, int64_t n, int64_t ldk, double* out, hipStream_t s);
 
+// CNN-VEC NNGP (cv.hip): per-image tables [img][layer][pixel] float2 and
+// K(x, x), then one N-lane segment per pair.
+int launch_cv_prepare(const float* x, int64_t n, int N, int C, int D, double sw2, double sb2, float2* tab,
+                      float* kdiag, hipStream_t s);
+int launch_cv_pairs(int N, const float* x1, const float* x2, int64_t n1, int64_t n2, int sym, int T, int C, int D,
+                    const float2* tab1, const float2* tab2, float* K, int64_t ldk, float sb2, float seed_scale,
+                    hipStream_t s);
+
 }  // namespace nk

@@ -179,6 +179,29 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
     return dx1, dx2, ds
 
 
+def cv_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 8, sigma_w2: float = 2.0,
+            sigma_b2: float = 0.01, out: torch.Tensor | None = None) -> torch.Tensor:
+    """CNN-VEC (CV8 for depth 8) NNGP block of NHWC images; x2 None or x1
+    gives the symmetric block."""
+    if x2 is None:
+        x2 = x1
+    _check_images(x1, "x1")
+    _check_images(x2, "x2")
+    if x1.shape[1:] != x2.shape[1:]:
+        raise ValueError("image shapes differ")
+    n1, h, w, c = (int(v) for v in x1.shape)
+    n2 = int(x2.shape[0])
+    cfg = _lib.CvCfg(h, w, c, int(depth), float(sigma_w2), float(sigma_b2))
+    sym = x1.data_ptr() == x2.data_ptr() and n1 == n2
+    if out is None:
+        out = torch.empty((n1, n2), dtype=torch.float32, device=x1.device)
+    ws = workspace(workspace_size(_lib.NK_OP_CV, cfg, n1, 0 if sym else n2), x1.device)
+    rc = _lib.lib().nk_cv_nngp(x1.data_ptr(), n1, x2.data_ptr(), n2, ctypes.byref(cfg), out.data_ptr(),
+                               out.stride(0), ws.data_ptr(), ws.numel(), _stream(x1.device))
+    _lib.check(rc)
+    return out
+
+
 def _check_gram(k: torch.Tensor) -> tuple[int, int]:
     """(n, ldk) of a float32 CUDA n x n matrix with unit column stride."""
     if not isinstance(k, torch.Tensor) or not k.is_cuda or k.dtype != torch.float32:

@@ -40,3 +40,10 @@ def kernel_storage_bytes(n_examples: int, bytes_per_entry: int = 8) -> float:
 
 def upper_triangle_blocks(n_examples: int, block: int) -> float:
     return (n_examples / block) ** 2 / 2
+
+
+def cv_flops_per_pair(hw: int, c: int, depth: int) -> int:
+    """CNN-VEC (flatten readout): the displacement-0 map of h w entries per
+    layer, the seed's channel products, and the readout sum."""
+    n2 = hw * hw
+    return FLOPS_PER_ENTRY_LAYER * depth * n2 + FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c * n2 + FLOPS_PER_POOLED_ENTRY * n2

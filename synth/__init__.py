@@ -105,6 +105,9 @@ WORKLOADS = {
                              seeds=(4001, 4002, 4003), n_tiles=64, lo=32, hi=2048,
                              depth=(2, 2, 2), sigma_w2=2.0, sigma_b2=0.0,
                              big_hw=64, big_n=256, big_length=6.0, big_seeds=(4004, 4005)),
+    # CV8 (CNN-VEC, depth 8, flatten readout) on 32x32x3 correlated images.
+    "cv8_32x32_4096": dict(kind="corr", n1=4096, n2=4096, hw=32, c=3, length=3.0, seeds=(7001, 7002),
+                           depth=8, sigma_w2=2.0, sigma_b2=0.01),
     # Kernel regression by preconditioned CG: a 32768 x 32768 float32 Gram
     # (the FC-3 NNGP of 32x32x3 correlated images) and 10 one-hot targets.
     "fc3_pcg_32768": dict(kind="corr", n=32768, hw=32, c=3, length=3.0, seeds=(6001, 6002),

@@ -168,3 +168,27 @@ def test_solver_workspace_and_validation():
     assert L.nk_krr_pcg(p, 100, 100, p, 10, 0.0, 0, ctypes.byref(cfg), p, None, None, ctypes.byref(st), p, ws,
                         None) == _lib.NK_EINVAL
     assert "lambda" in L.nk_last_error().decode()
+
+
+def test_cv_validation():
+    L = _lib.lib()
+    p = ctypes.c_void_p(256)
+    cfg = _lib.CvCfg(32, 32, 3, 8, 2.0, 0.01)
+    need = L.nk_workspace_size(_lib.NK_OP_CV, ctypes.byref(cfg), 100, 50)
+    sym = L.nk_workspace_size(_lib.NK_OP_CV, ctypes.byref(cfg), 100, 0)
+    assert need > sym >= 100 * 8 * 32 * 32 * 8
+    for bad, code in ((_lib.CvCfg(64, 64, 3, 8, 2.0, 0.01), _lib.NK_EUNSUPPORTED),
+                      (_lib.CvCfg(12, 12, 3, 8, 2.0, 0.01), _lib.NK_EUNSUPPORTED),
+                      (_lib.CvCfg(32, 16, 3, 8, 2.0, 0.01), _lib.NK_EUNSUPPORTED),
+                      (_lib.CvCfg(32, 32, 5, 8, 2.0, 0.01), _lib.NK_EUNSUPPORTED),
+                      (_lib.CvCfg(32, 32, 3, 17, 2.0, 0.01), _lib.NK_EUNSUPPORTED),
+                      (_lib.CvCfg(32, 32, 3, 0, 2.0, 0.01), _lib.NK_EINVAL),
+                      (_lib.CvCfg(32, 32, 3, 8, 0.0, 0.01), _lib.NK_EINVAL),
+                      (_lib.CvCfg(32, 32, 3, 8, 2.0, -1.0), _lib.NK_EINVAL)):
+        assert L.nk_cv_nngp(p, 4, p, 4, ctypes.byref(bad), p, 4, p, need, None) == code
+        assert L.nk_workspace_size(_lib.NK_OP_CV, ctypes.byref(bad), 4, 4) == 0
+    assert L.nk_cv_nngp(p, 4, p, 5, ctypes.byref(cfg), p, 4, p, need, None) == _lib.NK_EINVAL  # ldk < n2
+    assert L.nk_cv_nngp(p, 0, p, 5, ctypes.byref(cfg), p, 5, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_cv_nngp(p, 4, p, 5, ctypes.byref(cfg), p, 5, p, 64, None) == _lib.NK_EINVAL
+    assert "workspace" in L.nk_last_error().decode()
+    assert L.nk_cv_nngp(None, 4, p, 5, ctypes.byref(cfg), p, 5, p, need, None) == _lib.NK_EINVAL
