@@ -25,6 +25,9 @@ Contents
   recursion for tiny images, used to pin the C loop nest.
 * ``solvers`` (submodule) -- the partial pivoted Cholesky preconditioner and
   preconditioned conjugate gradients in float64 (Sec. 2, iterative solvers).
+* ``approx`` (submodule) -- Nystrom, subset of regressors, block-diagonal and
+  Bayesian-committee-machine predictions in float64 (Sec. 2, approximations
+  to the linear system).
 """
 from __future__ import annotations
 
