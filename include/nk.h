@@ -64,7 +64,8 @@ enum {
   NK_OP_PCG = 6,          /* cfg: nk_pcg_cfg; n1 = n, n2 = c */
   NK_OP_PIVOTED_CHOL = 7, /* cfg: NULL; n1 = n, n2 = rank */
   NK_OP_GRAM_MATVEC = 8,  /* cfg: NULL; n1 = n, n2 = c */
-  NK_OP_CV = 9            /* cfg: nk_cv_cfg; n1, n2 = block sizes (n2 = 0 for a symmetric block) */
+  NK_OP_CV = 9,           /* cfg: nk_cv_cfg; n1, n2 = block sizes (n2 = 0 for a symmetric block) */
+  NK_OP_APPROX = 10       /* cfg: nk_approx_dims; n1, n2 unused */
 };
 
 /*
@@ -354,6 +355,65 @@ typedef struct {
 int nk_krr_pcg(const float* K, int64_t n, int64_t ldk, const double* Y, int64_t c, double ridge,
                int ridge_is_relative, const nk_pcg_cfg* cfg, double* X, int32_t* iters, double* relres,
                nk_pcg_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Approximate kernel ridge regression: the four approximations to the
+ * linear system the paper compares with CG (Sec. 2, "Approximations to the
+ * linear system"), in the forms of Rasmussen and Williams, "Gaussian
+ * Processes for Machine Learning", ch. 8 (which the paper cites).  None of
+ * them needs the whole training Gram.  The subset (Nystrom, subset of
+ * regressors) or the partition (block-diagonal, committee machine) is the
+ * caller's choice -- the paper draws it uniformly at random -- and is given
+ * through the kernel blocks passed in: a subset as its kernel columns, a
+ * partition by ordering the training points block by block.
+ *
+ * All kernel blocks and Y are float32 device arrays, row-major with the
+ * given leading dimensions (Y: n x c, leading dim c); pred is m x c float32
+ * (leading dim c).  Sums and solves run in float64; the sums whose results
+ * are later subtracted from nearly equal quantities are compensated.
+ * lambda > 0 is the ridge; jitter >= 0 is added to the diagonal of the
+ * matrix a method inverts besides its ridge system (K_rr, or the committee
+ * machine's test covariances).  Each call synchronises `stream` and returns
+ * NK_ENOTPD if a Cholesky factorisation meets a non-positive pivot.
+ * Workspace: nk_workspace_size(NK_OP_APPROX, &dims, 0, 0) with
+ * dims = {n, r, m, c, largest block}.
+ */
+typedef struct {
+  int64_t n, r, m, c, max_block;
+} nk_approx_dims;
+
+/* Nystrom: the training kernel replaced by K_nr (K_rr + jitter I)^{-1} K_rn;
+ * pred = K_mn (K~ + lambda I)^{-1} Y, through the Woodbury identity in
+ * O(n r^2).  K_nr: n x r (training vs subset), K_rr: r x r, K_mn: m x n
+ * (test vs all training points). */
+int nk_krr_nystrom(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
+                   const float* K_mn, int64_t m, int64_t ld_mn, const float* Y, int64_t c, double lambda,
+                   double jitter, float* pred, void* ws, size_t ws_bytes, void* stream);
+
+/* Subset of regressors: pred = K_mr (K_rn K_nr + lambda (K_rr + jitter I))^{-1}
+ * K_rn Y.  K_mr: m x r (test vs subset). */
+int nk_krr_sor(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
+               const float* K_mr, int64_t m, int64_t ld_mr, const float* Y, int64_t c, double lambda, double jitter,
+               float* pred, void* ws, size_t ws_bytes, void* stream);
+
+/* Block-diagonal: p blocks of sizes[i] consecutive training points;
+ * alpha_i = (K_ii + lambda I)^{-1} Y_i; pred = K_mn alpha.  K_blocks: host
+ * array of p device pointers, block i sizes[i] x sizes[i] (leading dim
+ * sizes[i]); sizes: host array summing to n; K_mn: m x n (columns in block
+ * order). */
+int nk_krr_block_diag(int32_t p, const float* const* K_blocks, const int64_t* sizes, const float* K_mn, int64_t m,
+                      int64_t ld_mn, const float* Y, int64_t c, double lambda, float* pred, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Bayesian committee machine, posterior mean of the m test points taken
+ * jointly: per block mu_i = K_mi (K_ii + lambda I)^{-1} Y_i and
+ * S_i = K_mm - K_mi (K_ii + lambda I)^{-1} K_im;
+ * S^{-1} = sum_i (S_i + jitter I)^{-1} - (p - 1) (K_mm + jitter I)^{-1};
+ * pred = S sum_i (S_i + jitter I)^{-1} mu_i.  Blocks as in
+ * nk_krr_block_diag; K_mm: m x m test-test kernel. */
+int nk_krr_bcm(int32_t p, const float* const* K_blocks, const int64_t* sizes, const float* K_mn, int64_t m,
+               int64_t ld_mn, const float* K_mm, int64_t ld_mm, const float* Y, int64_t c, double lambda,
+               double jitter, float* pred, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing (tracing).  After nk_profile_enable(1), every launch of the

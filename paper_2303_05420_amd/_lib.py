@@ -28,6 +28,7 @@ NK_OP_PCG = 6
 NK_OP_PIVOTED_CHOL = 7
 NK_OP_GRAM_MATVEC = 8
 NK_OP_CV = 9
+NK_OP_APPROX = 10
 
 
 class MyrtleCfg(ctypes.Structure):
@@ -54,6 +55,11 @@ class BatchedCandidate(ctypes.Structure):
 class CvCfg(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("sigma_w2", ctypes.c_float), ("sigma_b2", ctypes.c_float)]
+
+
+class ApproxDims(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("r", ctypes.c_int64), ("m", ctypes.c_int64), ("c", ctypes.c_int64),
+                ("max_block", ctypes.c_int64)]
 
 
 class PcgCfg(ctypes.Structure):
@@ -116,6 +122,14 @@ def lib():
     dbl = ctypes.c_double
     L.nk_cv_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(CvCfg), P, i64, P, sz, P]
     L.nk_cv_nngp.restype = ci
+    L.nk_krr_nystrom.argtypes = [P, i64, i64, i64, P, i64, P, i64, i64, P, i64, dbl, dbl, P, P, sz, P]
+    L.nk_krr_nystrom.restype = ci
+    L.nk_krr_sor.argtypes = [P, i64, i64, i64, P, i64, P, i64, i64, P, i64, dbl, dbl, P, P, sz, P]
+    L.nk_krr_sor.restype = ci
+    L.nk_krr_block_diag.argtypes = [i32, P, P, P, i64, i64, P, i64, dbl, P, P, sz, P]
+    L.nk_krr_block_diag.restype = ci
+    L.nk_krr_bcm.argtypes = [i32, P, P, P, i64, i64, P, i64, P, i64, dbl, dbl, P, P, sz, P]
+    L.nk_krr_bcm.restype = ci
     L.nk_pivoted_cholesky.argtypes = [P, i64, i64, i32, dbl, P, P, ctypes.POINTER(i32), P, sz, P]
     L.nk_pivoted_cholesky.restype = ci
     L.nk_gram_matvec.argtypes = [P, i64, i64, P, i64, dbl, P, P, sz, P]

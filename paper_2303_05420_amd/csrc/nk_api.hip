@@ -587,6 +587,86 @@ CvPlan cv_plan(const nk_cv_cfg* c, int64_t n1, int64_t n2, bool sym) {
   return p;
 }
 
+// ---- approximate kernel ridge regression ---------------------------------
+
+constexpr int64_t kApproxMaxSolve = 8192;  // sides of the matrices factored in LDS-held solves
+
+struct ApproxPlan {
+  size_t A, D, b, v, alpha, P, rhs2, Z, mu, S, Sinv, Kinv, I, prec, acc, info, total;
+};
+
+ApproxPlan approx_plan(const nk_approx_dims& d) {
+  ApproxPlan p{};
+  Bump b;
+  const size_t r = (size_t)std::max<int64_t>(d.r, 1), n = (size_t)std::max<int64_t>(d.n, 1);
+  const size_t m = (size_t)std::max<int64_t>(d.m, 1), c = (size_t)std::max<int64_t>(d.c, 1);
+  const size_t mb = (size_t)std::max<int64_t>(std::max(d.max_block, d.r), 1);
+  p.A = b.take(sizeof(double) * r * r);
+  p.D = b.take(sizeof(double) * mb * mb);
+  p.b = b.take(sizeof(double) * r * c);
+  p.v = b.take(sizeof(double) * r * c);
+  p.alpha = b.take(sizeof(double) * n * c);
+  p.P = b.take(sizeof(double) * m * c);
+  p.rhs2 = b.take(sizeof(double) * mb * (c + m));
+  p.Z = b.take(sizeof(double) * mb * (c + m));
+  p.mu = b.take(sizeof(double) * m * c);
+  p.S = b.take(sizeof(double) * m * m);
+  p.Sinv = b.take(sizeof(double) * m * m);
+  p.Kinv = b.take(sizeof(double) * m * m);
+  p.I = b.take(sizeof(double) * m * m);
+  p.prec = b.take(sizeof(double) * m * m);
+  p.acc = b.take(sizeof(double) * m * c);
+  p.info = b.take(sizeof(int) * 4);
+  p.total = b.off + 256;
+  return p;
+}
+
+int approx_finish(hipStream_t s, const int* info_dev, const char* what) {
+  int info = 0;
+  if (hipMemcpyAsync(&info, info_dev, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return hip_fail(what);
+  if (info) return fail(NK_ENOTPD, "%s: a factorised matrix is not positive definite", what);
+  return ok();
+}
+
+// Nystrom and SoR share v = (K_rn K_nr + lam (K_rr + jitter I))^{-1} K_rn Y.
+int approx_low_rank_v(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
+                      const float* Y, int64_t c, double lam, double jitter, void* ws, const ApproxPlan& ap,
+                      hipStream_t s) {
+  double* A = at<double>(ws, ap.A);
+  double* D = at<double>(ws, ap.D);
+  double* bb = at<double>(ws, ap.b);
+  int* info = at<int>(ws, ap.info);
+  if (nk::dn_gemm_ff(K_nr, ld_nr, true, K_nr, ld_nr, A, r, r, r, n, 1.0, 0.0, true, s) ||
+      nk::dn_load_shift(K_rr, ld_rr, r, jitter, D, info, s) || nk::dn_axpby(A, D, r * r, 1.0, lam, s) ||
+      nk::dn_gemm_ff(K_nr, ld_nr, true, Y, c, bb, c, r, c, n, 1.0, 0.0, true, s) ||
+      nk::launch_cholesky(A, r, info, s) ||
+      nk::launch_chol_solve(A, r, nullptr, bb, c, at<double>(ws, ap.v), s))
+    return -3;
+  return 0;
+}
+
+int check_approx_common(int64_t n, int64_t m, int64_t c, double lam, double jitter, const float* Y, float* pred) {
+  if (!Y || !pred) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || m <= 0 || c <= 0) return fail(NK_EINVAL, "need n, m, c > 0");
+  if (!(lam > 0.0) || !(jitter >= 0.0)) return fail(NK_EINVAL, "need lambda > 0 and jitter >= 0");
+  return 0;
+}
+
+int check_blocks(int32_t p, const float* const* K_blocks, const int64_t* sizes, int64_t* n, int64_t* maxb) {
+  if (p <= 0 || !K_blocks || !sizes) return fail(NK_EINVAL, "need p > 0 blocks with pointers and sizes");
+  *n = 0;
+  *maxb = 0;
+  for (int32_t i = 0; i < p; ++i) {
+    if (!K_blocks[i] || sizes[i] <= 0) return fail(NK_EINVAL, "block %d: null pointer or size <= 0", i);
+    *n += sizes[i];
+    *maxb = std::max(*maxb, sizes[i]);
+  }
+  if (*maxb > kApproxMaxSolve) return fail(NK_EUNSUPPORTED, "block larger than %lld", (long long)kApproxMaxSolve);
+  return 0;
+}
+
 // ---- kernel regression by preconditioned conjugate gradients --------------
 
 constexpr int kPcgMaxRank = 8192;  // LDS of a pivot step holds one row of L
@@ -759,6 +839,11 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
     case NK_OP_GRAM_MATVEC:
       if (n1 <= 0) return 0;
       return pcg_plan(n1, 0, 2).total;
+    case NK_OP_APPROX: {
+      const nk_approx_dims* d = static_cast<const nk_approx_dims*>(cfg);
+      if (!d || d->n <= 0 || d->m <= 0 || d->c <= 0 || d->r < 0 || d->max_block < 0) return 0;
+      return approx_plan(*d).total;
+    }
     case NK_OP_CV: {
       const nk_cv_cfg* c = static_cast<const nk_cv_cfg*>(cfg);
       if (check_cv(c) || n1 <= 0 || n2 < 0) return 0;
@@ -1055,6 +1140,142 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
   return ok();
 }
 
+
+
+int nk_krr_nystrom(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
+                   const float* K_mn, int64_t m, int64_t ld_mn, const float* Y, int64_t c, double lambda,
+                   double jitter, float* pred, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_approx_common(n, m, c, lambda, jitter, Y, pred);
+  if (rc) return rc;
+  if (!K_nr || !K_rr || !K_mn) return fail(NK_EINVAL, "null pointer argument");
+  if (r <= 0 || r > n || ld_nr < r || ld_rr < r || ld_mn < n) return fail(NK_EINVAL, "bad r or leading dimension");
+  if (r > kApproxMaxSolve) return fail(NK_EUNSUPPORTED, "r > %lld", (long long)kApproxMaxSolve);
+  const nk_approx_dims d{n, r, m, c, 0};
+  const ApproxPlan ap = approx_plan(d);
+  if (!ws || ws_bytes < ap.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", ap.total);
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("krr_nystrom", s);
+  double* alpha = at<double>(ws, ap.alpha);
+  double* P = at<double>(ws, ap.P);
+  if (approx_low_rank_v(K_nr, n, r, ld_nr, K_rr, ld_rr, Y, c, lambda, jitter, ws, ap, s) ||
+      nk::dn_gemm_fd(K_nr, ld_nr, false, at<double>(ws, ap.v), c, alpha, c, n, c, r, 1.0, 0.0, true, s) ||
+      nk::dn_residual_scale(Y, c, n, c, 1.0 / lambda, alpha, s) ||
+      nk::dn_gemm_fd(K_mn, ld_mn, false, alpha, c, P, c, m, c, n, 1.0, 0.0, false, s) ||
+      nk::dn_cast(P, m, c, pred, c, s))
+    return hip_fail("nystrom");
+  return approx_finish(s, at<int>(ws, ap.info), "nystrom");
+}
+
+int nk_krr_sor(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
+               const float* K_mr, int64_t m, int64_t ld_mr, const float* Y, int64_t c, double lambda, double jitter,
+               float* pred, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_approx_common(n, m, c, lambda, jitter, Y, pred);
+  if (rc) return rc;
+  if (!K_nr || !K_rr || !K_mr) return fail(NK_EINVAL, "null pointer argument");
+  if (r <= 0 || r > n || ld_nr < r || ld_rr < r || ld_mr < r) return fail(NK_EINVAL, "bad r or leading dimension");
+  if (r > kApproxMaxSolve) return fail(NK_EUNSUPPORTED, "r > %lld", (long long)kApproxMaxSolve);
+  const nk_approx_dims d{n, r, m, c, 0};
+  const ApproxPlan ap = approx_plan(d);
+  if (!ws || ws_bytes < ap.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", ap.total);
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("krr_sor", s);
+  double* P = at<double>(ws, ap.P);
+  if (approx_low_rank_v(K_nr, n, r, ld_nr, K_rr, ld_rr, Y, c, lambda, jitter, ws, ap, s) ||
+      nk::dn_gemm_fd(K_mr, ld_mr, false, at<double>(ws, ap.v), c, P, c, m, c, r, 1.0, 0.0, false, s) ||
+      nk::dn_cast(P, m, c, pred, c, s))
+    return hip_fail("sor");
+  return approx_finish(s, at<int>(ws, ap.info), "sor");
+}
+
+int nk_krr_block_diag(int32_t p, const float* const* K_blocks, const int64_t* sizes, const float* K_mn, int64_t m,
+                      int64_t ld_mn, const float* Y, int64_t c, double lambda, float* pred, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int64_t n = 0, maxb = 0;
+  int rc = check_blocks(p, K_blocks, sizes, &n, &maxb);
+  if (rc) return rc;
+  rc = check_approx_common(n, m, c, lambda, 0.0, Y, pred);
+  if (rc) return rc;
+  if (!K_mn || ld_mn < n) return fail(NK_EINVAL, "K_mn is NULL or ld_mn < n");
+  const nk_approx_dims d{n, 0, m, c, maxb};
+  const ApproxPlan ap = approx_plan(d);
+  if (!ws || ws_bytes < ap.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", ap.total);
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("krr_block_diag", s);
+  double* D = at<double>(ws, ap.D);
+  double* alpha = at<double>(ws, ap.alpha);
+  double* P = at<double>(ws, ap.P);
+  int* info = at<int>(ws, ap.info);
+  int64_t off = 0;
+  for (int32_t i = 0; i < p; ++i) {
+    const int64_t b = sizes[i];
+    if (nk::dn_load_shift(K_blocks[i], b, b, lambda, D, i == 0 ? info : nullptr, s) ||
+        nk::launch_cholesky(D, b, info, s) ||
+        nk::launch_chol_solve(D, b, Y + off * c, nullptr, c, alpha + off * c, s))
+      return hip_fail("block diagonal");
+    off += b;
+  }
+  if (nk::dn_gemm_fd(K_mn, ld_mn, false, alpha, c, P, c, m, c, n, 1.0, 0.0, false, s) ||
+      nk::dn_cast(P, m, c, pred, c, s))
+    return hip_fail("block diagonal");
+  return approx_finish(s, info, "block diagonal");
+}
+
+int nk_krr_bcm(int32_t p, const float* const* K_blocks, const int64_t* sizes, const float* K_mn, int64_t m,
+               int64_t ld_mn, const float* K_mm, int64_t ld_mm, const float* Y, int64_t c, double lambda,
+               double jitter, float* pred, void* ws, size_t ws_bytes, void* stream) {
+  int64_t n = 0, maxb = 0;
+  int rc = check_blocks(p, K_blocks, sizes, &n, &maxb);
+  if (rc) return rc;
+  rc = check_approx_common(n, m, c, lambda, jitter, Y, pred);
+  if (rc) return rc;
+  if (!K_mn || ld_mn < n || !K_mm || ld_mm < m) return fail(NK_EINVAL, "bad K_mn or K_mm");
+  if (m > kApproxMaxSolve) return fail(NK_EUNSUPPORTED, "m > %lld", (long long)kApproxMaxSolve);
+  const nk_approx_dims d{n, 0, m, c, maxb};
+  const ApproxPlan ap = approx_plan(d);
+  if (!ws || ws_bytes < ap.total) return fail(NK_EINVAL, "workspace too small (need %zu bytes)", ap.total);
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps("krr_bcm", s);
+  double* D = at<double>(ws, ap.D);
+  double* RHS = at<double>(ws, ap.rhs2);
+  double* Z = at<double>(ws, ap.Z);
+  double* mu = at<double>(ws, ap.mu);
+  double* S = at<double>(ws, ap.S);
+  double* Sinv = at<double>(ws, ap.Sinv);
+  double* Kinv = at<double>(ws, ap.Kinv);
+  double* I = at<double>(ws, ap.I);
+  double* prec = at<double>(ws, ap.prec);
+  double* acc = at<double>(ws, ap.acc);
+  double* P = at<double>(ws, ap.P);
+  int* info = at<int>(ws, ap.info);
+  const int64_t w = c + m;
+  // prior precision of the test values: (K_mm + jitter I)^{-1}; prec = -(p - 1) of it
+  if (nk::dn_identity(I, m, s) || nk::dn_load_shift(K_mm, ld_mm, m, jitter, S, info, s) ||
+      nk::launch_cholesky(S, m, info, s) || nk::launch_chol_solve(S, m, nullptr, I, m, Kinv, s) ||
+      nk::dn_axpby(prec, Kinv, m * m, 0.0, -(double)(p - 1), s) || nk::launch_zero_f64(acc, m * c, s))
+    return hip_fail("bcm");
+  int64_t off = 0;
+  for (int32_t i = 0; i < p; ++i) {
+    const int64_t b = sizes[i];
+    const float* kmi = K_mn + off;  // columns off .. off + b of K_mn
+    if (nk::dn_load_shift(K_blocks[i], b, b, lambda, D, nullptr, s) || nk::launch_cholesky(D, b, info, s) ||
+        nk::dn_copy_f(Y + off * c, c, b, c, false, RHS, w, s) ||
+        nk::dn_copy_f(kmi, ld_mn, b, m, true, RHS + c, w, s) ||
+        nk::launch_chol_solve(D, b, nullptr, RHS, w, Z, s) ||
+        // mu_i = K_mi Z[:, :c];  S_i = K_mm - K_mi Z[:, c:] (a difference of nearly equal terms: compensated)
+        nk::dn_gemm_fd(kmi, ld_mn, false, Z, w, mu, c, m, c, b, 1.0, 0.0, false, s) ||
+        nk::dn_copy_f(K_mm, ld_mm, m, m, false, S, m, s) ||
+        nk::dn_gemm_fd(kmi, ld_mn, false, Z + c, w, S, m, m, m, b, -1.0, 1.0, true, s) ||
+        nk::dn_shift(S, m, jitter, nullptr, s) || nk::launch_cholesky(S, m, info, s) ||
+        nk::launch_chol_solve(S, m, nullptr, I, m, Sinv, s) || nk::dn_axpby(prec, Sinv, m * m, 1.0, 1.0, s) ||
+        nk::dn_gemm_dd(Sinv, m, false, mu, c, acc, c, m, c, m, 1.0, 1.0, false, s))
+      return hip_fail("bcm");
+    off += b;
+  }
+  if (nk::launch_cholesky(prec, m, info, s) || nk::launch_chol_solve(prec, m, nullptr, acc, c, P, s) ||
+      nk::dn_cast(P, m, c, pred, c, s))
+    return hip_fail("bcm");
+  return approx_finish(s, info, "bcm");
+}
 
 int nk_cv_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_cv_cfg* cfg, float* K,
                int64_t ldk, void* ws, size_t ws_bytes, void* stream) {

@@ -180,6 +180,24 @@ int launch_kmv(const float* K, int64_t n, int64_t ldk, const double* P, int C, d
                double* pq_part, hipStream_t s, ProfHook* hook);
 int launch_diag_mean(const float* K, int64_t n, int64_t ldk, double* out, hipStream_t s);
 
+// Dense float64 helpers of the approximate solvers (dense.hip).  GEMM:
+// C (M x N, ldc) = beta C + alpha op(A) B, op(A) = A (M x K) or A^T (A is
+// K x M); comp carries each sum's rounding error (compensated).
+int dn_gemm_ff(const float* A, int64_t lda, bool a_t, const float* B, int64_t ldb, double* C, int64_t ldc, int64_t M,
+               int64_t N, int64_t K, double alpha, double beta, bool comp, hipStream_t s);
+int dn_gemm_fd(const float* A, int64_t lda, bool a_t, const double* B, int64_t ldb, double* C, int64_t ldc,
+               int64_t M, int64_t N, int64_t K, double alpha, double beta, bool comp, hipStream_t s);
+int dn_gemm_dd(const double* A, int64_t lda, bool a_t, const double* B, int64_t ldb, double* C, int64_t ldc,
+               int64_t M, int64_t N, int64_t K, double alpha, double beta, bool comp, hipStream_t s);
+int dn_load_shift(const float* S, int64_t lds, int64_t n, double shift, double* D, int* info, hipStream_t s);
+int dn_shift(double* D, int64_t n, double shift, int* info, hipStream_t s);
+int dn_identity(double* I, int64_t n, hipStream_t s);
+int dn_copy_f(const float* in, int64_t ldi, int64_t rows, int64_t cols, bool trans, double* out, int64_t ldo,
+              hipStream_t s);
+int dn_residual_scale(const float* Y, int64_t ldy, int64_t n, int64_t c, double scale, double* X, hipStream_t s);
+int dn_cast(const double* in, int64_t rows, int64_t cols, float* out, int64_t ldo, hipStream_t s);
+int dn_axpby(double* D, const double* E, int64_t n, double alpha, double beta, hipStream_t s);
+
 // CNN-VEC NNGP (cv.hip): per-image tables [img][layer][pixel] float2 and
 // K(x, x), then one N-lane segment per pair.
 int launch_cv_prepare(const float* x, int64_t n, int N, int C, int D, double sw2, double sb2, float2* tab,

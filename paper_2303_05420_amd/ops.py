@@ -202,6 +202,85 @@ def cv_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 8, sigma_w2:
     return out
 
 
+def _f32_rows(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 \
+            or t.stride(1) != 1:
+        raise TypeError(f"{name} must be a 2-D float32 CUDA tensor with contiguous rows")
+    return int(t.shape[0]), int(t.shape[1]), int(t.stride(0))
+
+
+def _approx_ws(n, r, m, c, maxb, device):
+    d = _lib.ApproxDims(int(n), int(r), int(m), int(c), int(maxb))
+    return workspace(workspace_size(_lib.NK_OP_APPROX, d, 0, 0), device)
+
+
+def krr_nystrom(k_nr, k_rr, k_mn, y, lam: float, jitter: float = 1e-6) -> torch.Tensor:
+    """Nystrom kernel ridge regression prediction (float32 m x c)."""
+    n, r, ldnr = _f32_rows(k_nr, "k_nr")
+    _, _, ldrr = _f32_rows(k_rr, "k_rr")
+    m, _, ldmn = _f32_rows(k_mn, "k_mn")
+    _, c, _ = _f32_rows(y, "y")
+    pred = torch.empty((m, c), dtype=torch.float32, device=y.device)
+    ws = _approx_ws(n, r, m, c, 0, y.device)
+    rc = _lib.lib().nk_krr_nystrom(k_nr.data_ptr(), n, r, ldnr, k_rr.data_ptr(), ldrr, k_mn.data_ptr(), m, ldmn,
+                                   y.contiguous().data_ptr(), c, float(lam), float(jitter), pred.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), _stream(y.device))
+    _lib.check(rc)
+    return pred
+
+
+def krr_sor(k_nr, k_rr, k_mr, y, lam: float, jitter: float = 1e-6) -> torch.Tensor:
+    """Subset-of-regressors prediction (float32 m x c)."""
+    n, r, ldnr = _f32_rows(k_nr, "k_nr")
+    _, _, ldrr = _f32_rows(k_rr, "k_rr")
+    m, _, ldmr = _f32_rows(k_mr, "k_mr")
+    _, c, _ = _f32_rows(y, "y")
+    pred = torch.empty((m, c), dtype=torch.float32, device=y.device)
+    ws = _approx_ws(n, r, m, c, 0, y.device)
+    rc = _lib.lib().nk_krr_sor(k_nr.data_ptr(), n, r, ldnr, k_rr.data_ptr(), ldrr, k_mr.data_ptr(), m, ldmr,
+                               y.contiguous().data_ptr(), c, float(lam), float(jitter), pred.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream(y.device))
+    _lib.check(rc)
+    return pred
+
+
+def _blocks(blocks):
+    ptrs = (ctypes.c_void_p * len(blocks))(*[b.data_ptr() for b in blocks])
+    sizes = (ctypes.c_int64 * len(blocks))(*[int(b.shape[0]) for b in blocks])
+    for b in blocks:
+        if not b.is_cuda or b.dtype != torch.float32 or not b.is_contiguous() or b.shape[0] != b.shape[1]:
+            raise TypeError("blocks must be square contiguous float32 CUDA tensors")
+    return ptrs, sizes, sum(int(b.shape[0]) for b in blocks), max(int(b.shape[0]) for b in blocks)
+
+
+def krr_block_diag(blocks, k_mn, y, lam: float) -> torch.Tensor:
+    """Block-diagonal approximation; training points ordered block by block."""
+    ptrs, sizes, n, maxb = _blocks(blocks)
+    m, _, ldmn = _f32_rows(k_mn, "k_mn")
+    _, c, _ = _f32_rows(y, "y")
+    pred = torch.empty((m, c), dtype=torch.float32, device=y.device)
+    ws = _approx_ws(n, 0, m, c, maxb, y.device)
+    rc = _lib.lib().nk_krr_block_diag(len(blocks), ptrs, sizes, k_mn.data_ptr(), m, ldmn, y.contiguous().data_ptr(),
+                                      c, float(lam), pred.data_ptr(), ws.data_ptr(), ws.numel(), _stream(y.device))
+    _lib.check(rc)
+    return pred
+
+
+def krr_bcm(blocks, k_mn, k_mm, y, lam: float, jitter: float = 0.0) -> torch.Tensor:
+    """Bayesian committee machine posterior mean of the test points (jointly)."""
+    ptrs, sizes, n, maxb = _blocks(blocks)
+    m, _, ldmn = _f32_rows(k_mn, "k_mn")
+    _, _, ldmm = _f32_rows(k_mm, "k_mm")
+    _, c, _ = _f32_rows(y, "y")
+    pred = torch.empty((m, c), dtype=torch.float32, device=y.device)
+    ws = _approx_ws(n, 0, m, c, maxb, y.device)
+    rc = _lib.lib().nk_krr_bcm(len(blocks), ptrs, sizes, k_mn.data_ptr(), m, ldmn, k_mm.data_ptr(), ldmm,
+                               y.contiguous().data_ptr(), c, float(lam), float(jitter), pred.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream(y.device))
+    _lib.check(rc)
+    return pred
+
+
 def _check_gram(k: torch.Tensor) -> tuple[int, int]:
     """(n, ldk) of a float32 CUDA n x n matrix with unit column stride."""
     if not isinstance(k, torch.Tensor) or not k.is_cuda or k.dtype != torch.float32:

@@ -192,3 +192,32 @@ def test_cv_validation():
     assert L.nk_cv_nngp(p, 4, p, 5, ctypes.byref(cfg), p, 5, p, 64, None) == _lib.NK_EINVAL
     assert "workspace" in L.nk_last_error().decode()
     assert L.nk_cv_nngp(None, 4, p, 5, ctypes.byref(cfg), p, 5, p, need, None) == _lib.NK_EINVAL
+
+
+def test_approx_validation():
+    L = _lib.lib()
+    p = ctypes.c_void_p(256)
+    d = _lib.ApproxDims(100, 10, 20, 3, 0)
+    need = L.nk_workspace_size(_lib.NK_OP_APPROX, ctypes.byref(d), 0, 0)
+    assert need > 100 * 3 * 8
+    bad = _lib.ApproxDims(0, 10, 20, 3, 0)
+    assert L.nk_workspace_size(_lib.NK_OP_APPROX, ctypes.byref(bad), 0, 0) == 0
+    assert L.nk_krr_nystrom(p, 100, 10, 9, p, 10, p, 20, 100, p, 3, 1e-3, 1e-6, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_nystrom(p, 100, 101, 101, p, 101, p, 20, 100, p, 3, 1e-3, 1e-6, p, p, need,
+                            None) == _lib.NK_EINVAL
+    assert L.nk_krr_nystrom(p, 100, 10, 10, p, 10, p, 20, 100, p, 3, 0.0, 1e-6, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_sor(p, 100, 10, 10, p, 10, p, 20, 9, p, 3, 1e-3, 1e-6, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_sor(p, 100, 10, 10, p, 10, p, 20, 10, p, 3, 1e-3, -1.0, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_sor(p, 100, 10, 10, p, 10, p, 20, 10, p, 3, 1e-3, 1e-6, p, p, 64, None) == _lib.NK_EINVAL
+    blocks = (ctypes.c_void_p * 2)(256, 256)
+    sizes = (ctypes.c_int64 * 2)(60, 40)
+    assert L.nk_krr_block_diag(0, blocks, sizes, p, 20, 100, p, 3, 1e-3, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_block_diag(2, blocks, sizes, p, 20, 99, p, 3, 1e-3, p, p, need, None) == _lib.NK_EINVAL
+    sizes[1] = 0
+    assert L.nk_krr_block_diag(2, blocks, sizes, p, 20, 100, p, 3, 1e-3, p, p, need, None) == _lib.NK_EINVAL
+    sizes[1] = 40
+    assert L.nk_krr_bcm(2, blocks, sizes, p, 20, 100, p, 19, p, 3, 1e-3, 0.0, p, p, need, None) == _lib.NK_EINVAL
+    assert L.nk_krr_bcm(2, blocks, sizes, p, 20, 100, p, 20, p, 3, 1e-3, 0.0, p, p, 64, None) == _lib.NK_EINVAL
+    sizes[0] = 10000
+    assert L.nk_krr_bcm(2, blocks, sizes, p, 20, 10040, p, 20, p, 3, 1e-3, 0.0, p, p, need,
+                        None) == _lib.NK_EUNSUPPORTED
