@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Myrtle-10 NNGP kernel entries/s at 32x32x3; fwd+bwd pairs/s; %FP32 VALU peak"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA, 64 lanes)
 PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_hbm_counters.md")
-STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage.hip")
+STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage_kernel.h")
 
 
 def _args():
@@ -45,6 +45,7 @@ def _args():
     p.add_argument("--no-ntk", action="store_true", help="skip the Myrtle-10 NTK measurement")
     p.add_argument("--no-pcg", action="store_true", help="skip the preconditioned-CG solve measurement")
     p.add_argument("--no-cv8", action="store_true", help="skip the CV8 NNGP measurement")
+    p.add_argument("--no-approx", action="store_true", help="skip the approximate-solver measurement")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -238,6 +239,72 @@ def _cv8(torch, cpu: bool):
     return res
 
 
+def _approx(torch):
+    """The four approximate solvers on 32768 training points (FC-3 NNGP of the
+    PCG workload's images) and 2048 test images: Nystrom and SoR with a random
+    subset of 2048, block-diagonal and the committee machine with a random
+    partition into 16 blocks of 2048.  Kernel blocks are built on the GPU
+    before the timed calls; each method is timed once after an untimed call.
+    Model flops (multiply-adds counted twice) of each method's float64
+    products and factorisations are reported against the 78.6 TFLOP/s FP64
+    vector peak."""
+    import numpy as np
+
+    import synth
+    from paper_2303_05420_amd import ops
+
+    w = synth.WORKLOADS["fc3_approx_32768"]
+    n, m, r, p = w["n"], w["m"], w["rank"], w["blocks"]
+    c = w["n_classes"]
+    xs = synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][0])
+    xt = synth.correlated_images(m, 32, 32, 3, w["length"], w["seeds"][3])
+    y = torch.from_numpy(synth.teacher_labels(xs, c, w["seeds"][1])).cuda()
+    x = torch.from_numpy(xs.reshape(n, -1)).cuda()
+    xm = torch.from_numpy(xt.reshape(m, -1)).cuda()
+    fc = dict(depth=w["fc_depth"], sigma_w2=w["fc_sigma_w2"], sigma_b2=w["fc_sigma_b2"])
+    rng = np.random.default_rng(w["seeds"][2])
+    sub = torch.from_numpy(rng.choice(n, r, replace=False)).cuda()
+    perm = torch.from_numpy(np.random.default_rng(w["seeds"][4]).permutation(n)).cuda()
+    k_nr = ops.fc_nngp(x, x[sub].contiguous(), **fc)
+    k_rr = ops.fc_nngp(x[sub].contiguous(), None, **fc)
+    k_mn = ops.fc_nngp(xm, x, **fc)
+    k_mr = k_mn[:, sub].contiguous()
+    k_mm = ops.fc_nngp(xm, None, **fc)
+    diag_mean = float(torch.diagonal(k_rr).double().mean())  # lambda from the subset's diagonal
+    lam = w["ridge_rel"] * diag_mean
+    xp = x[perm].contiguous()
+    yp = y[perm].contiguous()
+    b = n // p
+    blocks = [ops.fc_nngp(xp[i * b:(i + 1) * b].contiguous(), None, **fc) for i in range(p)]
+    k_mp = k_mn[:, perm].contiguous()
+    runs = {
+        "nystrom": (lambda: ops.krr_nystrom(k_nr, k_rr, k_mn, y, lam, w["jitter"]),
+                    2.0 * n * r * r + 2.0 * n * r * c * 2 + r ** 3 / 3 + 2.0 * m * n * c),
+        "sor": (lambda: ops.krr_sor(k_nr, k_rr, k_mr, y, lam, w["jitter"]),
+                2.0 * n * r * r + 2.0 * n * r * c + r ** 3 / 3 + 2.0 * m * r * c),
+        "block_diag": (lambda: ops.krr_block_diag(blocks, k_mp, yp, lam),
+                       p * (b ** 3 / 3 + 2.0 * b * b * c) + 2.0 * m * n * c),
+        "bcm": (lambda: ops.krr_bcm(blocks, k_mp, k_mm, yp, lam, w["jitter"]),
+                p * (b ** 3 / 3 + 2.0 * b * b * (c + m) + 2.0 * m * b * (c + m) + m ** 3 / 3 + 2.0 * m ** 3)
+                + 4.0 * m ** 3 / 3),
+    }
+    out = {"workload": f"approximate KRR on {n} training points (FC-3 NNGP of 32x32x3 correlated images), "
+                       f"{m} test points, {c} targets: Nystrom / SoR with a random subset of {r}, block-diagonal / "
+                       f"committee machine with a random partition into {p} blocks of {b}",
+           "lambda": lam}
+    for name, (fn, flops) in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"ms": round(dt * 1e3, 3), "model_tflops": round(flops / dt / 1e12, 3),
+                     "frac_fp64_peak": round(flops / dt / 1e12 / 78.6, 4)}
+        print(f"approx {name}: {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def _pcg(torch, cpu: bool):
     """Kernel regression by FP64 preconditioned CG on a 32768 x 32768 float32
     Gram (FC-3 NNGP of the workload's images, built on the GPU before the
@@ -422,6 +489,7 @@ def main():
     ntk = None if a.no_ntk else _ntk(torch)
     pcg = None if a.no_pcg else _pcg(torch, not a.no_cpu_baseline)
     cv8 = None if a.no_cv8 else _cv8(torch, not a.no_cpu_baseline)
+    approx = None if a.no_approx else _approx(torch)
 
     cpu = None
     parity = None
@@ -472,6 +540,7 @@ def main():
         "ntk": ntk,
         "pcg": pcg,
         "cv8": cv8,
+        "approx_solvers": approx,
         "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
     }
     print(json.dumps(rec))

@@ -113,6 +113,13 @@ WORKLOADS = {
     "fc3_pcg_32768": dict(kind="corr", n=32768, hw=32, c=3, length=3.0, seeds=(6001, 6002),
                           fc_depth=3, fc_sigma_w2=2.0, fc_sigma_b2=0.01, ridge_rel=1e-4,
                           n_classes=10, rank=512, tol=1e-8, max_iter=3000, cpu_n=4096),
+    # Approximate solvers on the PCG workload's training images: random
+    # subset of 2048 points (Nystrom, SoR), random partition into 16 blocks of
+    # 2048 (block-diagonal, committee machine), 2048 test images.
+    "fc3_approx_32768": dict(kind="corr", n=32768, m=2048, hw=32, c=3, length=3.0,
+                             seeds=(6001, 6002, 6003, 6004, 6005), rank=2048, blocks=16,
+                             fc_depth=3, fc_sigma_w2=2.0, fc_sigma_b2=0.01, ridge_rel=1e-4, jitter=1e-6,
+                             n_classes=10),
     # Myrtle-5 KRR distillation: 256 support + 2048 targets at 32x32x3.
     "myrtle5_krr_grad": dict(kind="corr", n_support=256, n_target=2048, hw=32, c=3,
                              length=3.0, seeds=(5001, 5002, 5003, 5004),
