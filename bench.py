@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Myrtle-10 NNGP kernel entries/s at 32x32x3; fwd+bwd pairs/s; %FP32 VALU peak"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 flop/clk (packed FMA, 64 lanes)
 PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_hbm_counters.md")
+PCG_PMC_FILE = os.path.join(ROOT, "profiles", "pcg_kmv_32768_hbm_counters.md")
+PCG_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "pcg.hip")
 STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage_kernel.h")
 
 
@@ -69,6 +71,19 @@ def _traffic(stage_launch_pairs: int):
     if per_pair is None:
         return None
     return float(per_pair) * stage_launch_pairs
+
+
+def _pcg_traffic(n: int):
+    """HBM bytes per K.P launch from the committed counter summary, or None when
+    there is none, it was taken at another size, or pcg.hip changed since."""
+    try:
+        text = open(PCG_PMC_FILE).read()
+        d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
+    if d.get("pcg_src_sha256_16") != _src_hash(PCG_SRC) or d.get("n") != n:
+        return None
+    return d.get("hbm_bytes_per_dispatch")
 
 
 def _fwd_bwd(torch):
@@ -367,7 +382,7 @@ def _pcg(torch, cpu: bool):
            "setup_ms": round(setup_ms, 3), "ms_per_iteration": round((dt * 1e3 - setup_ms) / max(it_max, 1), 4),
            "kernels_ms": {kk: round(v[1], 3) for kk, v in prof.items()},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                        "frac": round(achieved / 8000.0, 4), "traffic": None,
+                        "frac": round(achieved / 8000.0, 4), "traffic": _pcg_traffic(n),
                         "kernel": f"kmv_partial_kernel<{w['n_classes']}, true> (K.P)",
                         "avg_launch_ms": round(mv_ms, 4), "algorithmic_bytes_per_launch": bytes_per_launch}}
     if cpu:
