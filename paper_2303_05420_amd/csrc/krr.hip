@@ -7,9 +7,8 @@
 //
 // Blocked right-looking Cholesky (block NB): factor the diagonal block in LDS,
 // solve the panel below it, update the trailing lower triangle; then copy L^T
-// into the strict upper triangle so the forward substitution reads rows.
-// Substitutions run one workgroup per right-hand side column with the
-// vector in LDS.
+// into the strict upper triangle.  Substitutions are blocked the same way:
+// panel triangles one thread per right-hand side, the rest by float64 GEMM.
 #include "nk_kernels.h"
 
 namespace nk {
@@ -90,15 +89,23 @@ __global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, 
   __syncthreads();
   const int64_t i = k + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
+  // (loops fully unrolled so that x stays in registers)
   double x[CH_NB];
   double* row = A + i * n + k;
-  for (int j = 0; j < nb; ++j) x[j] = row[j];
-  for (int j = 0; j < nb; ++j) {
-    double v = x[j];
-    for (int t = 0; t < j; ++t) v -= x[t] * L[j][t];
-    x[j] = v / L[j][j];
+#pragma unroll
+  for (int j = 0; j < CH_NB; ++j) x[j] = j < nb ? row[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < CH_NB; ++j) {
+    if (j < nb) {
+      double v = x[j];
+#pragma unroll
+      for (int t = 0; t < j; ++t) v = fma(-x[t], L[j][t], v);
+      x[j] = v / L[j][j];
+    }
   }
-  for (int j = 0; j < nb; ++j) row[j] = x[j];
+#pragma unroll
+  for (int j = 0; j < CH_NB; ++j)
+    if (j < nb) row[j] = x[j];
 }
 
 // Trailing update: A[i][j] -= sum_t A[i][k+t] A[j][k+t] for k+nb <= j <= i < n.
@@ -131,36 +138,6 @@ __global__ __launch_bounds__(256) void chol_mirror_kernel(double* __restrict__ A
   if (e >= n * n) return;
   const int64_t i = e / n, j = e - i * n;
   if (j > i) A[i * n + j] = A[j * n + i];
-}
-
-// Solve L L^T X = B for one column of B per workgroup; B is float (ld = c)
-// or double (ld = c); X written as double (n x c).
-__global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ A, int64_t n,
-                                                          const float* __restrict__ Bf,
-                                                          const double* __restrict__ Bd, int64_t c,
-                                                          double* __restrict__ X) {
-  extern __shared__ double y[];
-  const int64_t col = blockIdx.x;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int64_t i = tid; i < n; i += nt) y[i] = Bf ? (double)Bf[i * c + col] : Bd[i * c + col];
-  __syncthreads();
-  // forward: L z = y, L[i][t] = A[t][i] (upper copy) for i > t
-  for (int64_t t = 0; t < n; ++t) {
-    const double zt = y[t] / A[t * n + t];
-    __syncthreads();
-    if (tid == 0) y[t] = zt;
-    for (int64_t i = t + 1 + tid; i < n; i += nt) y[i] -= A[t * n + i] * zt;
-    __syncthreads();
-  }
-  // backward: L^T a = z, (L^T)[t][i] = L[i][t]; row t of L is A[t][0..t]
-  for (int64_t t = n - 1; t >= 0; --t) {
-    const double at = y[t] / A[t * n + t];
-    __syncthreads();
-    if (tid == 0) y[t] = at;
-    for (int64_t i = tid; i < t; i += nt) y[i] -= A[t * n + i] * at;
-    __syncthreads();
-  }
-  for (int64_t i = tid; i < n; i += nt) X[i * c + col] = y[i];
 }
 
 // out (m x c, float) = K (m x n, float, leading dim ld) X (n x c, double)
@@ -261,18 +238,84 @@ int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// ---- blocked substitution for many right-hand sides ----------------------
+//
+// X = A^{-1} B with A = L L^T factored in place (L in the lower triangle):
+// forward L Z = B and backward L^T X = Z in panels of CH_NB rows.  Each
+// panel's triangle is solved with one thread per right-hand side (the
+// triangle in LDS, the panel's unknowns in registers), and the rows not yet
+// solved are updated with the float64 GEMM (X_rest -= L_rest,panel X_panel).
+
+// X (n x c double) = B (float or double, n x c)
+__global__ __launch_bounds__(256) void chol_rhs_copy_kernel(const float* __restrict__ Bf,
+                                                            const double* __restrict__ Bd, int64_t nc,
+                                                            double* __restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < nc) X[e] = Bf ? (double)Bf[e] : Bd[e];
+}
+
+// Triangle of panel [k, k + nb) for every column: forward (L) or backward (L^T).
+template <bool BACK>
+__global__ __launch_bounds__(256) void chol_panel_kernel(const double* __restrict__ A, int64_t n, int64_t k, int nb,
+                                                         double* __restrict__ X, int64_t c) {
+  __shared__ double T[CH_NB][CH_NB + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    T[i][j] = j <= i ? A[(k + i) * n + k + j] : 0.0;  // L of the panel
+  }
+  __syncthreads();
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= c) return;
+  double x[CH_NB];
+#pragma unroll
+  for (int i = 0; i < CH_NB; ++i) x[i] = i < nb ? X[(k + i) * c + col] : 0.0;
+  if (!BACK) {
+#pragma unroll
+    for (int i = 0; i < CH_NB; ++i) {
+      if (i < nb) {
+        double v = x[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) v = fma(-T[i][j], x[j], v);
+        x[i] = v / T[i][i];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = CH_NB - 1; i >= 0; --i) {
+      if (i < nb) {
+        double v = x[i];
+#pragma unroll
+        for (int j = i + 1; j < CH_NB; ++j)
+          if (j < nb) v = fma(-T[j][i], x[j], v);
+        x[i] = v / T[i][i];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CH_NB; ++i)
+    if (i < nb) X[(k + i) * c + col] = x[i];
+}
+
 int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double* Bd, int64_t c, double* X,
                       hipStream_t s) {
-  const size_t lds = (size_t)n * sizeof(double);
-  static size_t attr_bytes = 0;
-  if (lds > 64 * 1024 && attr_bytes < lds) {
-    if (hipFuncSetAttribute((const void*)chol_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
+  if (n <= 0 || c <= 0) return 0;
+  hipLaunchKernelGGL(chol_rhs_copy_kernel, dim3((unsigned)((n * c + 255) / 256)), dim3(256), 0, s, Bf, Bd, n * c, X);
+  const unsigned gc = (unsigned)((c + 255) / 256);
+  for (int64_t k = 0; k < n; k += CH_NB) {
+    const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
+    hipLaunchKernelGGL(chol_panel_kernel<false>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
+    const int64_t rest = n - k - nb;
+    if (rest > 0 && dn_gemm_dd(A + (k + nb) * n + k, n, false, X + k * c, c, X + (k + nb) * c, c, rest, c, nb, -1.0,
+                               1.0, false, s))
       return -3;
-    attr_bytes = lds;
   }
-  hipLaunchKernelGGL(chol_solve_kernel, dim3((unsigned)c), dim3(1024), (size_t)n * sizeof(double), s, A, n, Bf, Bd,
-                     c, X);
+  const int64_t last = ((n - 1) / CH_NB) * CH_NB;
+  for (int64_t k = last; k >= 0; k -= CH_NB) {
+    const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
+    hipLaunchKernelGGL(chol_panel_kernel<true>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
+    // rows [0, k): X -= (L[k:k+nb, 0:k])^T X_panel
+    if (k > 0 && dn_gemm_dd(A + k * n, n, true, X + k * c, c, X, c, k, c, nb, -1.0, 1.0, false, s)) return -3;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
