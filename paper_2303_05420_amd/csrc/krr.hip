@@ -296,26 +296,35 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const double* __restric
     if (i < nb) X[(k + i) * c + col] = x[i];
 }
 
+int launch_tri_solve(const double* A, int64_t n, double* X, int64_t c, bool upper, hipStream_t s) {
+  if (n <= 0 || c <= 0) return 0;
+  const unsigned gc = (unsigned)((c + 255) / 256);
+  if (!upper) {
+    for (int64_t k = 0; k < n; k += CH_NB) {
+      const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
+      hipLaunchKernelGGL(chol_panel_kernel<false>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
+      const int64_t rest = n - k - nb;
+      if (rest > 0 && dn_gemm_dd(A + (k + nb) * n + k, n, false, X + k * c, c, X + (k + nb) * c, c, rest, c, nb,
+                                 -1.0, 1.0, false, s))
+        return -3;
+    }
+  } else {
+    const int64_t last = ((n - 1) / CH_NB) * CH_NB;
+    for (int64_t k = last; k >= 0; k -= CH_NB) {
+      const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
+      hipLaunchKernelGGL(chol_panel_kernel<true>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
+      // rows [0, k): X -= (L[k:k+nb, 0:k])^T X_panel
+      if (k > 0 && dn_gemm_dd(A + k * n, n, true, X + k * c, c, X, c, k, c, nb, -1.0, 1.0, false, s)) return -3;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double* Bd, int64_t c, double* X,
                       hipStream_t s) {
   if (n <= 0 || c <= 0) return 0;
   hipLaunchKernelGGL(chol_rhs_copy_kernel, dim3((unsigned)((n * c + 255) / 256)), dim3(256), 0, s, Bf, Bd, n * c, X);
-  const unsigned gc = (unsigned)((c + 255) / 256);
-  for (int64_t k = 0; k < n; k += CH_NB) {
-    const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
-    hipLaunchKernelGGL(chol_panel_kernel<false>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
-    const int64_t rest = n - k - nb;
-    if (rest > 0 && dn_gemm_dd(A + (k + nb) * n + k, n, false, X + k * c, c, X + (k + nb) * c, c, rest, c, nb, -1.0,
-                               1.0, false, s))
-      return -3;
-  }
-  const int64_t last = ((n - 1) / CH_NB) * CH_NB;
-  for (int64_t k = last; k >= 0; k -= CH_NB) {
-    const int nb = (int)((n - k) < CH_NB ? (n - k) : CH_NB);
-    hipLaunchKernelGGL(chol_panel_kernel<true>, dim3(gc), dim3(256), 0, s, A, n, k, nb, X, c);
-    // rows [0, k): X -= (L[k:k+nb, 0:k])^T X_panel
-    if (k > 0 && dn_gemm_dd(A + k * n, n, true, X + k * c, c, X, c, k, c, nb, -1.0, 1.0, false, s)) return -3;
-  }
+  if (launch_tri_solve(A, n, X, c, false, s) || launch_tri_solve(A, n, X, c, true, s)) return -3;
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

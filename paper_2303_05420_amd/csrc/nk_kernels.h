@@ -125,6 +125,9 @@ int launch_cast_grad(const double* src, float* dst, int64_t n, hipStream_t s);
 int launch_finish_sigma(const double* sums, double sw2, float* dsigma, hipStream_t s);
 int launch_zero_f64(double* p, int64_t n, hipStream_t s);
 int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s);
+// In place X (n x c, row-major) <- L^{-1} X (upper = false) or L^{-T} X
+// (upper = true), L the factor launch_cholesky left in A.
+int launch_tri_solve(const double* A, int64_t n, double* X, int64_t c, bool upper, hipStream_t s);
 int launch_chol_solve(const double* A, int64_t n, const float* Bf, const double* Bd, int64_t c, double* X,
                       hipStream_t s);
 int launch_krr_build(const float* K, int64_t n, double ridge_rel, double lam_abs, double* mean, double* A,

@@ -16,10 +16,11 @@
 //     updates d.  Picked indices hold d = -inf.
 //   * The preconditioner Ph = L L^T + lam I is applied with the Woodbury
 //     identity Ph^{-1} v = (v - L M^{-1} L^T v) / lam, M = lam I + L^T L.
-//     With M = R R^T (Cholesky) and U = L R^{-T}, formed once in place of L,
-//     this is (v - U (U^T v)) / lam: two skinny products per application and
-//     an operator that stays symmetric in floating point (an explicitly
-//     inverted M does not, and CG then stalls above small tolerances).
+//     With M = R R^T (Cholesky) and U = L R^{-T}, formed once in place of L
+//     by a blocked forward substitution, this is (v - U (U^T v)) / lam: two
+//     skinny products per application and an operator that stays symmetric
+//     in floating point (an explicitly inverted M does not, and CG then
+//     stalls above small tolerances).
 //   * kmv_*: Q = (K + lam I) P, the product that dominates each iteration:
 //     K is streamed once from HBM as float4 rows.  Because K is symmetric,
 //     Q[i] = sum_j K[j][i] P[j]: lane l of a wave owns columns 4l..4l+3 of a
@@ -309,27 +310,15 @@ __global__ __launch_bounds__(PC_TPB) void pc_ltl_kernel(const double* __restrict
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) info[0] = 0;
 }
 
-// U = L R^{-T} in place (L column major n x r; R the lower Cholesky factor of
-// M, stored in M's lower triangle): row i of U solves R u = l_i by forward
-// substitution, one thread per row.
-__global__ __launch_bounds__(PC_TPB) void pc_u_kernel(double* __restrict__ LU, int64_t n, int r,
-                                                      const double* __restrict__ R) {
-  const int64_t i = (int64_t)blockIdx.x * PC_TPB + threadIdx.x;
-  if (i >= n) return;
-  for (int a = 0; a < r; ++a) {
-    const double* ra = R + (int64_t)a * r;
-    double s = LU[(int64_t)a * n + i];
-    for (int b = 0; b < a; ++b) s = fma(-ra[b], LU[(int64_t)b * n + i], s);
-    LU[(int64_t)a * n + i] = s / ra[a];
-  }
-}
-
 int launch_pc_setup(double* LU, int64_t n, int r, double lam, double* Ur, double* M, int* info, hipStream_t s) {
   if (r == 0) return 0;
   const unsigned g = (unsigned)((r + 31) / 32);
   hipLaunchKernelGGL(pc_ltl_kernel, dim3(g, g), dim3(PC_TPB), 0, s, LU, n, r, lam, M, info);
   if (launch_cholesky(M, r, info, s)) return -3;
-  hipLaunchKernelGGL(pc_u_kernel, dim3((unsigned)((n + PC_TPB - 1) / PC_TPB)), dim3(PC_TPB), 0, s, LU, n, r, M);
+  // U = L R^{-T} in place: with L stored column major (an r x n row-major
+  // array), U^T = R^{-1} L^T is a forward substitution with n right-hand
+  // sides, run blocked (panel triangles and float64 GEMM updates)
+  if (launch_tri_solve(M, r, LU, n, false, s)) return -3;
   hipLaunchKernelGGL(pc_transpose_kernel, dim3((unsigned)((n + 31) / 32), (unsigned)((r + 31) / 32)), dim3(PC_TPB),
                      0, s, LU, n, r, Ur);
   return hipGetLastError() == hipSuccess ? 0 : -3;
