@@ -67,36 +67,112 @@ struct CvArgs {
   float* K;
   int64_t ldk;
   float sb2, seed_scale;
-  int64_t np;
+  int64_t nb1, nb2, nblocks;  // 4 x 4 pair blocks per side, and in the pass
 };
 
-// Pairs per workgroup: 256 / N segments of N lanes.
-template <int N, bool BIAS>
-__global__ __launch_bounds__(256) void cv_pair_kernel(const CvArgs a) {
-  constexpr int SEGS = 256 / N;
-  const int seg = threadIdx.x / N, ix = threadIdx.x - seg * N;
-  const int64_t p = (int64_t)xcd_logical_block() * SEGS + seg;
-  const bool valid = p < a.np;
-  int64_t ia = 0, ib = 0;
-  pair_of(valid ? p : a.np - 1, a.n1, a.n2, a.sym, a.T, &ia, &ib);
-  const float* p1 = a.x1 + (ia * N * N + ix) * a.C;
-  const float* p2 = a.x2 + (ib * N * N + ix) * a.C;
+// Workgroup shape.  A workgroup computes a block of 4 x 4 pairs (images
+// 4 bi + 0..3 of x1 against 4 bj + 0..3 of x2), one N-lane segment per pair,
+// so that the tables of 8 images serve 16 pairs.  Each layer's tables of the
+// 8 images sit in LDS (8 N^2 float2: 64 KiB at N = 32); the next layer's are
+// fetched into registers while the current layer is
+// computed, and written to LDS between two barriers.
+template <int N>
+struct CvB {
+  static constexpr int PAIRS = 16;
+  static constexpr int THREADS = PAIRS * N < 64 ? 64 : PAIRS * N;
+  static constexpr int NN = N * N;
+  static constexpr size_t LDS = (size_t)8 * NN * sizeof(float2);
+};
+
+template <int N, int C, bool BIAS>
+__global__ __launch_bounds__(CvB<N>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void cv_block_kernel(const CvArgs a) {
+  using B = CvB<N>;
+  constexpr int NN = B::NN, THREADS = B::THREADS, HALF = NN / 2;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  float2* lds = reinterpret_cast<float2*>(smem);
+  float4* lds4 = reinterpret_cast<float4*>(smem);
+  const int tid = threadIdx.x;
+  const int q = tid / N, ix = tid - q * N;
+  const int qa = (q >> 2) & 3, qb = q & 3;
+  int64_t bi, bj;
+  pair_of(xcd_logical_block(), a.nb1, a.nb2, a.sym, a.T, &bi, &bj);
+  const int64_t ia = bi * 4 + qa, ib = bj * 4 + qb;
+  // a pair outside the block (ragged edge, or below the diagonal of a
+  // symmetric diagonal block) runs on clamped images and writes nothing
+  const bool valid = q < B::PAIRS && ia < a.n1 && ib < a.n2 && !(a.sym && bi == bj && qa > qb);
+  const int64_t iac = ia < a.n1 ? ia : a.n1 - 1, ibc = ib < a.n2 ? ib : a.n2 - 1;
+
+  // staging: THREADS / 8 threads per table slot (slots 0..3: images 4 bi + s
+  // of x1, 4..7: images 4 bj + s - 4 of x2), each moving NV float4 of it
+  constexpr int TPS = THREADS / 8, NV = (HALF + TPS - 1) / TPS;
+  const int sl = tid / TPS, sj = tid - sl * TPS;
+  const float4* src;
+  {
+    int64_t img = sl < 4 ? bi * 4 + sl : bj * 4 + (sl - 4);
+    const int64_t lim = sl < 4 ? a.n1 : a.n2;
+    if (img >= lim) img = lim - 1;
+    src = reinterpret_cast<const float4*>(sl < 4 ? a.tab1 : a.tab2) + img * (int64_t)a.D * HALF + sj;
+  }
+  float4* dst = lds4 + sl * HALF + sj;
+  // (plain floats: an array of float4 structs is not kept in registers)
+  float pf[NV][4];
+#define CV_FETCH(l)                                                                          \
+  _Pragma("unroll") for (int m = 0; m < NV; ++m) if (HALF % TPS == 0 || sj + m * TPS < HALF) { \
+    const float4 v = src[(int64_t)(l) * HALF + m * TPS];                                     \
+    pf[m][0] = v.x;                                                                          \
+    pf[m][1] = v.y;                                                                          \
+    pf[m][2] = v.z;                                                                          \
+    pf[m][3] = v.w;                                                                          \
+  }
+#define CV_STORE()                                                                           \
+  _Pragma("unroll") for (int m = 0; m < NV; ++m) if (HALF % TPS == 0 || sj + m * TPS < HALF) \
+      dst[m * TPS] = make_float4(pf[m][0], pf[m][1], pf[m][2], pf[m][3])
+
+  // seed: the pixels of SR rows are requested together, then combined
+  constexpr int SR = N < 4 ? N : 4;
+  const float* p1 = a.x1 + (iac * NN + ix) * C;
+  const float* p2 = a.x2 + (ibc * NN + ix) * C;
   float A[N];
 #pragma unroll
-  for (int r = 0; r < N; ++r) {
-    float s = 0.f;
-    for (int c = 0; c < a.C; ++c) s = __builtin_fmaf(p1[r * N * a.C + c], p2[r * N * a.C + c], s);
-    A[r] = s * a.seed_scale;
+  for (int r0 = 0; r0 < N; r0 += SR) {
+    float u[SR][C], w[SR][C];
+#pragma unroll
+    for (int k = 0; k < SR; ++k)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        u[k][c] = p1[(r0 + k) * N * C + c];
+        w[k][c] = p2[(r0 + k) * N * C + c];
+      }
+#pragma unroll
+    for (int k = 0; k < SR; ++k) {
+      float sd = 0.f;
+#pragma unroll
+      for (int c = 0; c < C; ++c) sd = __builtin_fmaf(u[k][c], w[k][c], sd);
+      A[r0 + k] = sd * a.seed_scale;
+    }
   }
+  CV_FETCH(0);
+  CV_STORE();
+  __syncthreads();
+
   const float mL = ix >= 1 ? 1.f : 0.f;
   const float mR = ix + 1 < N ? 1.f : 0.f;
-  const float2* c1 = a.tab1 + ia * (int64_t)a.D * N * N + ix;
-  const float2* c2 = a.tab2 + ib * (int64_t)a.D * N * N + ix;
-  tile_layer<N, true, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
-  for (int l = 1; l < a.D; ++l) {
-    c1 += N * N;
-    c2 += N * N;
-    tile_layer<N, false, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
+  const float2* c1 = lds + qa * NN + ix;
+  const float2* c2 = lds + (4 + qb) * NN + ix;
+  for (int l = 0; l < a.D; ++l) {
+    if (l + 1 < a.D) {
+      CV_FETCH(l + 1);
+    }
+    if (l == 0)
+      tile_layer<N, true, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
+    else
+      tile_layer<N, false, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
+    if (l + 1 < a.D) {
+      __syncthreads();
+      CV_STORE();
+      __syncthreads();
+    }
   }
   // readout: the tile's sum (its scale rides on the last layer's tables)
   float t[N];
@@ -116,6 +192,8 @@ __global__ __launch_bounds__(256) void cv_pair_kernel(const CvArgs a) {
     if (a.sym && ia != ib) a.K[ib * a.ldk + ia] = kv;
   }
 }
+#undef CV_FETCH
+#undef CV_STORE
 
 size_t cv_prepare_lds_bytes(int N) { return (size_t)2 * N * N * sizeof(double); }
 
@@ -127,15 +205,25 @@ int launch_cv_prepare(const float* x, int64_t n, int N, int C, int D, double sw2
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+template <int N, int C>
+int launch_cv_pairs_nc(const CvArgs& a, bool bias, hipStream_t s) {
+  using B = CvB<N>;
+  if (bias)
+    hipLaunchKernelGGL((cv_block_kernel<N, C, true>), dim3((unsigned)a.nblocks), dim3(B::THREADS), B::LDS, s, a);
+  else
+    hipLaunchKernelGGL((cv_block_kernel<N, C, false>), dim3((unsigned)a.nblocks), dim3(B::THREADS), B::LDS, s, a);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 template <int N>
 int launch_cv_pairs_n(const CvArgs& a, bool bias, hipStream_t s) {
-  constexpr int SEGS = 256 / N;
-  const int64_t nwg = (a.np + SEGS - 1) / SEGS;
-  if (bias)
-    hipLaunchKernelGGL((cv_pair_kernel<N, true>), dim3((unsigned)nwg), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((cv_pair_kernel<N, false>), dim3((unsigned)nwg), dim3(256), 0, s, a);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
+  switch (a.C) {
+    case 1: return launch_cv_pairs_nc<N, 1>(a, bias, s);
+    case 2: return launch_cv_pairs_nc<N, 2>(a, bias, s);
+    case 3: return launch_cv_pairs_nc<N, 3>(a, bias, s);
+    case 4: return launch_cv_pairs_nc<N, 4>(a, bias, s);
+    default: return -1;
+  }
 }
 
 int launch_cv_pairs(int N, const float* x1, const float* x2, int64_t n1, int64_t n2, int sym, int T, int C, int D,
@@ -156,8 +244,11 @@ int launch_cv_pairs(int N, const float* x1, const float* x2, int64_t n1, int64_t
   a.ldk = ldk;
   a.sb2 = sb2;
   a.seed_scale = seed_scale;
-  a.np = pair_count(n1, n2, sym);
-  if (a.np <= 0) return 0;
+  a.nb1 = (n1 + 3) / 4;
+  a.nb2 = (n2 + 3) / 4;
+  a.nblocks = pair_count(a.nb1, a.nb2, sym);
+  if (a.nblocks <= 0) return 0;
+  if (a.nblocks > 0x7fffffff) return -1;
   const bool bias = sb2 != 0.f;
   switch (N) {
     case 2: return launch_cv_pairs_n<2>(a, bias, s);
