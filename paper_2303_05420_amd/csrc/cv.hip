@@ -82,7 +82,47 @@ struct CvB {
   static constexpr int THREADS = PAIRS * N < 64 ? 64 : PAIRS * N;
   static constexpr int NN = N * N;
   static constexpr size_t LDS = (size_t)8 * NN * sizeof(float2);
+  static constexpr int RH = N / 2;  // row before which the next layer's tables are requested
 };
+
+// One [3x3 conv, ReLU] layer of a displacement-0 tile (no seam: the
+// vertical links are all present).  The next layer's table float4s of this
+// thread (src + m * TPS, m < NV) are requested before row RH, so that the
+// registers they land in are live for the rest of the layer only.
+template <int N, bool SIGNED, bool BIAS, int RH, int NV, int TPS, bool FULL>
+__device__ __forceinline__ void cv_layer(float (&A)[N], const float2* __restrict__ c1,
+                                         const float2* __restrict__ c2, float mL, float mR, float sb2,
+                                         const float4* __restrict__ src, int sj, int half, float (&pf)[NV][4]) {
+  float hm = 0.f;
+  float h0 = hsum3(A[0], mL, mR);
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    if (r == RH) {
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (FULL || sj + m * TPS < half) {
+          const float4 v = src[m * TPS];
+          pf[m][0] = v.x;
+          pf[m][1] = v.y;
+          pf[m][2] = v.z;
+          pf[m][3] = v.w;
+        }
+    }
+    float hp = 0.f;
+    if (r + 1 < N) hp = hsum3(A[r + 1], mL, mR);
+    float v = h0;
+    if (r > 0) v += hm;
+    if (r + 1 < N) v += hp;
+    if (BIAS) v += sb2;
+    const float2 ta = c1[r * N];
+    const float2 tb = c2[r * N];
+    const float rr = ta.x * tb.x;
+    const float J = SIGNED ? j1_signed_vr(v, rr) : j1_nonneg(v * rr);
+    A[r] = (ta.y * tb.y) * J;
+    hm = h0;
+    h0 = hp;
+  }
+}
 
 template <int N, int C, bool BIAS>
 __global__ __launch_bounds__(CvB<N>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
@@ -160,14 +200,15 @@ void cv_block_kernel(const CvArgs a) {
   const float mR = ix + 1 < N ? 1.f : 0.f;
   const float2* c1 = lds + qa * NN + ix;
   const float2* c2 = lds + (4 + qb) * NN + ix;
+  constexpr bool FULL = HALF % TPS == 0;
   for (int l = 0; l < a.D; ++l) {
-    if (l + 1 < a.D) {
-      CV_FETCH(l + 1);
-    }
+    // (the last layer re-reads its own tables: always in bounds, never stored;
+    // a conditional fetch would keep the registers live across the layer)
+    const float4* nsrc = src + (int64_t)(l + 1 < a.D ? l + 1 : l) * HALF;
     if (l == 0)
-      tile_layer<N, true, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
+      cv_layer<N, true, BIAS, B::RH, NV, TPS, FULL>(A, c1, c2, mL, mR, a.sb2, nsrc, sj, HALF, pf);
     else
-      tile_layer<N, false, BIAS>(A, c1, c2, -1, mL, mR, a.sb2);
+      cv_layer<N, false, BIAS, B::RH, NV, TPS, FULL>(A, c1, c2, mL, mR, a.sb2, nsrc, sj, HALF, pf);
     if (l + 1 < a.D) {
       __syncthreads();
       CV_STORE();
