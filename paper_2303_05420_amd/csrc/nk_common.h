@@ -166,14 +166,17 @@ __device__ __forceinline__ float j1_signed(float rho) {
   return __builtin_fmaf(u * sq, relu_poly(u), __builtin_fmaxf(rho, 0.0f));
 }
 
-__device__ __forceinline__ float acos_g(float u) {
-  float p = NK_ACOS_C6;
-  p = __builtin_fmaf(p, u, NK_ACOS_C5);
-  p = __builtin_fmaf(p, u, NK_ACOS_C4);
-  p = __builtin_fmaf(p, u, NK_ACOS_C3);
-  p = __builtin_fmaf(p, u, NK_ACOS_C2);
-  p = __builtin_fmaf(p, u, NK_ACOS_C1);
-  p = __builtin_fmaf(p, u, NK_ACOS_C0);
+// acos(1 - u) / pi = sqrt(u) G(u) / pi, with 1/pi folded into the
+// coefficients of G.
+__device__ __forceinline__ float acos_g_pi(float u) {
+  constexpr float ip = 0.31830988618379067f;
+  float p = NK_ACOS_C6 * ip;
+  p = __builtin_fmaf(p, u, NK_ACOS_C5 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOS_C4 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOS_C3 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOS_C2 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOS_C1 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOS_C0 * ip);
   return p;
 }
 

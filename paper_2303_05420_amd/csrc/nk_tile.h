@@ -126,12 +126,12 @@ __device__ __forceinline__ void tile_layer_ntk(float (&A)[N], float (&C)[N], con
       const float cc = __builtin_amdgcn_fmed3f(__builtin_fmaf(v, rr, 1.0f), 0.0f, 1.0f);
       const float sq = __builtin_amdgcn_sqrtf(u);
       J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), cc);
-      th = sq * acos_g(u) * 0.31830988618379067f;
+      th = sq * acos_g_pi(u);
     } else {
       const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-v, rr, 1.0f), 0.0f, umax);
       const float sq = __builtin_amdgcn_sqrtf(u);
       J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), 1.0f);
-      th = sq * acos_g(u) * 0.31830988618379067f;
+      th = sq * acos_g_pi(u);
     }
     const float kfd = (SIGNED && v < 0.f) ? kh * th : __builtin_fmaf(-th, kh, kh);
     const float an = (a.y * b.y) * J;

@@ -50,11 +50,12 @@ struct BCfg {
 };
 
 // LDS per pair: tables x1 [D N^2 float2], tables x2 with rows twice
-// [2 D N^2 float2], images as float4 (first stage).  After the sweep the same
-// bytes hold the combined sums [w1: D N^2][w2: D N^2][xbar1: N^2 C][xbar2: N^2 C].
+// [2 D N^2 float2], images as float4 (first stage: x1, then x2 with its rows
+// twice, so that its rows are read without wrapping).  After the sweep the
+// same bytes hold the combined sums [w1: D N^2][w2: D N^2][xbar1: N^2 C][xbar2: N^2 C].
 template <int N>
 __host__ __device__ constexpr size_t bwd_slot_lds_bytes(int D, bool seed) {
-  return (((size_t)D * N * N * 24 + (seed ? (size_t)N * N * 32 : 0)) + 16 + 15) & ~(size_t)15;
+  return (((size_t)D * N * N * 24 + (seed ? (size_t)N * N * 48 : 0)) + 16 + 15) & ~(size_t)15;
 }
 
 // h-values of the rows just outside this lane's rows (the row above the first
@@ -135,7 +136,7 @@ __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[
     const float u = __builtin_amdgcn_fmed3f(1.0f - arho, 0.0f, 1.0f);
     const float sq = __builtin_amdgcn_sqrtf(u);
     const float J = __builtin_fmaf(u * sq, relu_poly(u), SGN ? __builtin_fmaxf(rho, 0.0f) : rho);
-    const float th = sq * acos_g(u) * 0.31830988618379067f;  // acos(|rho|) / pi
+    const float th = sq * acos_g_pi(u);  // acos(|rho|) / pi
     const float Jp = (SGN && rho < 0.f) ? th : 1.0f - th;
     const float out = ss * J;
     const float gb = G[rr];
@@ -257,6 +258,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
       }
       i1[px] = make_float4(u[0], u[1], u[2], u[3]);
       i1[NN + px] = make_float4(w[0], w[1], w[2], w[3]);
+      i1[2 * NN + px] = make_float4(w[0], w[1], w[2], w[3]);
     }
   }
   __syncthreads();
@@ -310,14 +312,14 @@ void stage_bwd_kernel(const StageBwdArgs args) {
       // loop are re-issued rather than kept live in registers across it.
       auto load_input = [&](float (&X)[RPL]) {
         if constexpr (SEED) {
+          // (row bases formed once: the rows are then constant offsets)
           const int z = opaque_zero();
-          const float4* im1 = img1 + z;
-          const float4* im2 = img2 + z;
+          const float4* im1 = img1 + z + row0 * N + ix;
+          const float4* im2 = img2 + z + (row0 + ky) * N + jx;
 #pragma unroll
           for (int rr = 0; rr < RPL; ++rr) {
-            const int r = row0 + rr;
-            const float4 u = im1[r * N + ix];
-            const float4 w = im2[((r + ky) & (N - 1)) * N + jx];
+            const float4 u = im1[rr * N];
+            const float4 w = im2[rr * N];
             X[rr] = ssd * __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
           }
         } else {
@@ -367,13 +369,12 @@ void stage_bwd_kernel(const StageBwdArgs args) {
       // G = adjoint of the stage input
       if constexpr (SEED) {
         const int z = opaque_zero();
-        const float4* im1 = img1 + z;
-        const float4* im2 = img2 + z;
+        const float4* im1 = img1 + z + row0 * N + ix;
+        const float4* im2 = img2 + z + (row0 + ky) * N + jx;
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
-          const int r = row0 + rr;
-          const float4 u = im1[r * N + ix];
-          const float4 w = im2[((r + ky) & (N - 1)) * N + jx];
+          const float4 u = im1[rr * N];
+          const float4 w = im2[rr * N];
           const float a0 = ssd * __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
           sw = __builtin_fmaf(G[rr], a0, sw);
           const float gb = G[rr] * ssd;
