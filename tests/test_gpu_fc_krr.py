@@ -24,7 +24,7 @@ def _gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("n1,n2,hw", [(1024, 1024, 32), (37, 51, 8), (1, 3, 5)])
+@pytest.mark.parametrize("n1,n2,hw", [(1024, 1024, 32), (37, 51, 8), (1, 3, 5), (300, 260, 7), (1100, 700, 16)])
 def test_fc3_matches_oracle(nk, n1, n2, hw):
     w = synth.WORKLOADS["fc3_myrtle5_32x32_1024"]
     x1 = synth.correlated_images(n1, hw, hw, 3, 3.0, w["seeds"][0])
