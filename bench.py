@@ -30,7 +30,9 @@ FP32_MFMA_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak of MI355X
 PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_hbm_counters.md")
 PCG_PMC_FILE = os.path.join(ROOT, "profiles", "pcg_kmv_32768_hbm_counters.md")
 PCG_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "pcg.hip")
-STAGE_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "stage_kernel.h")
+# the sources the stage-1 kernel is compiled from (its counters are void once any of them changes)
+STAGE_SRCS = [os.path.join(ROOT, "paper_2303_05420_amd", "csrc", f) for f in ("stage_kernel.h", "nk_tile.h", "nk_common.h")]
+VALU_PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_valu_counters.md")
 
 
 def _args():
@@ -54,24 +56,43 @@ def _args():
     return p.parse_args()
 
 
-def _src_hash(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def _src_hash(path) -> str:
+    h = hashlib.sha256()
+    for q in ([path] if isinstance(path, str) else path):
+        h.update(open(q, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _summary_json(path: str):
+    """The machine-readable block of a committed counter summary, or None."""
+    try:
+        text = open(path).read()
+        return json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
 
 
 def _traffic(stage_launch_pairs: int):
     """HBM bytes per stage-1 launch from the committed counter summary, or None
     when there is none or the kernel source changed since it was taken."""
-    try:
-        text = open(PMC_FILE).read()
-        d = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, ValueError, IndexError):
-        return None
-    if d.get("stage_src_sha256_16") != _src_hash(STAGE_SRC):
+    d = _summary_json(PMC_FILE)
+    if d is None or d.get("stage_src_sha256_16") != _src_hash(STAGE_SRCS):
         return None
     per_pair = d.get("hbm_bytes_per_pair")
     if per_pair is None:
         return None
     return float(per_pair) * stage_launch_pairs
+
+
+def _valu_counters():
+    """VALU counters of the stage-1 kernel from the committed summary (issued
+    FP32 flops against the op model, VALU busy), or None when there is none
+    or the kernel's sources changed since they were taken."""
+    d = _summary_json(VALU_PMC_FILE)
+    if d is None or d.get("stage_src_sha256_16") != _src_hash(STAGE_SRCS):
+        return None
+    return {k: d[k] for k in ("valu_busy_pct", "issued_over_algorithmic_flops", "valu_instructions_per_entry_layer",
+                              "fp32_instruction_mix") if k in d}
 
 
 def _pcg_traffic(n: int):
@@ -517,7 +538,7 @@ def main():
         traffic = _traffic(int(pairs_per_launch))
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": traffic, "kernel": f"myrtle_stage1_n{hw}",
+                "traffic": traffic, "valu_counters": _valu_counters(), "kernel": f"myrtle_stage1_n{hw}",
                 "avg_launch_ms": round(tot_ms / launches, 3), "pairs_per_launch": int(pairs_per_launch)}
     flops_pair = workmodel.flops_per_pair(hw, 3, depth)
     whole = flops_pair * pairs / (ms_step / 1e3) / 1e12
