@@ -38,7 +38,7 @@ VALU_PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_valu_counters.
 def _args():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=4096, help="block side (the headline workload is 4096)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -498,20 +498,20 @@ def main():
     torch.cuda.synchronize()
     _lib.profile_read(reset=True)
     _lib.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record()
+    evs[0].record()
     for i in range(a.steps):
         step()
-    e1.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _lib.profile_enable(False)
     prof = _lib.profile_read(reset=True)
-    ms_total = e0.elapsed_time(e1)
+    ms_total = evs[0].elapsed_time(evs[-1])
     ms_step = ms_total / a.steps
+    ms_each = [evs[i].elapsed_time(evs[i + 1]) for i in range(a.steps)]
     print(f"timed {a.steps} step(s): {ms_step:.1f} ms/step (wall {wall:.1f} s)", file=sys.stderr, flush=True)
 
     if a.copy_calib_mib:
@@ -581,6 +581,8 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms_step, 3),
+        "ms_each_step": [round(v, 3) for v in ms_each],
+        "ms_median_step": round(sorted(ms_each)[len(ms_each) // 2] if len(ms_each) % 2 else 0.5 * sum(sorted(ms_each)[len(ms_each) // 2 - 1:len(ms_each) // 2 + 1]), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
