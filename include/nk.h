@@ -81,8 +81,11 @@ enum {
  * least 2 x 2 (H >> (n_stages-1) >= 2), filter == 3, 1 <= n_stages <= 4,
  * 0 <= depth[s] <= 4 with depth[0] >= 1 (depth[0] <= 3 when H == 32: the
  * first stage keeps its tables and both images in LDS), 1 <= C <= 4,
- * sigma_w2 > 0, sigma_b2 >= 0.  Anything else returns NK_EUNSUPPORTED
- * (or NK_EINVAL for values that define no network).
+ * sigma_w2 > 0, sigma_b2 >= 0.  H == 64 is also accepted by nk_myrtle_nngp
+ * (and its workspace query) when n_stages >= 2 and depth[0] <= 2 (e.g.
+ * Myrtle-7 at 64x64x3); the tangent kernel, the adjoint and the batched
+ * pass return NK_EUNSUPPORTED for it.  Anything else returns
+ * NK_EUNSUPPORTED (or NK_EINVAL for values that define no network).
  */
 typedef struct {
   int32_t H, W, C, n_stages;

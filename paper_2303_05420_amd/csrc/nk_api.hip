@@ -87,13 +87,14 @@ struct Bump {
 
 constexpr int kPairTile = 16;           // images per side of a pair-order tile
 constexpr int64_t kDefaultChunk = 16384;  // pairs per stage pass for workspace queries
+constexpr int64_t kDefaultChunk64 = 1024;  // the same for 64x64 inputs (4 MiB of pooled output per pair)
 constexpr int64_t kPrepBlocks = 2048;     // images prepared per launch
 
 constexpr size_t kLdsDynamicMax = 160 * 1024 - 1024;  // dynamic LDS per workgroup
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
+int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net, bool allow64 = false) {
   if (!c) return fail(NK_EINVAL, "cfg is NULL");
   if (c->H <= 0 || c->W <= 0 || c->C <= 0 || c->n_stages <= 0)
     return fail(NK_EINVAL, "H, W, C and n_stages must be positive");
@@ -104,7 +105,12 @@ int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
   if (c->filter != 3) return fail(NK_EUNSUPPORTED, "only 3x3 filters are supported (filter = %d)", c->filter);
   if (c->H != c->W) return fail(NK_EUNSUPPORTED, "only square images are supported");
   if (c->C > 4) return fail(NK_EUNSUPPORTED, "at most 4 input channels are supported");
-  if (!is_pow2(c->H) || c->H > 32) return fail(NK_EUNSUPPORTED, "H must be a power of two <= 32 (H = %d)", c->H);
+  if (!is_pow2(c->H) || c->H > 64) return fail(NK_EUNSUPPORTED, "H must be a power of two <= 64 (H = %d)", c->H);
+  if (c->H == 64) {
+    if (!allow64) return fail(NK_EUNSUPPORTED, "64x64 inputs: only the NNGP block (nk_myrtle_nngp) supports them");
+    if (c->n_stages < 2) return fail(NK_EUNSUPPORTED, "64x64 inputs need at least two stages (the first one pools)");
+    if (c->depth[0] > 2) return fail(NK_EUNSUPPORTED, "64x64 inputs: at most 2 conv layers in the first stage");
+  }
   if ((c->H >> (c->n_stages - 1)) < 2)
     return fail(NK_EUNSUPPORTED, "the last stage must be at least 2 x 2 (H = %d, %d stages)", c->H, c->n_stages);
   if (c->depth[0] < 1) return fail(NK_EUNSUPPORTED, "the first stage needs at least one conv layer");
@@ -120,7 +126,8 @@ int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net) {
     const int N = net->hw >> s;
     const bool seed = s == 0, pool = s + 1 < net->S;
     // 160 KiB per workgroup, less 1 KiB for the kernels' static LDS
-    if (nk::stage_lds_bytes(N, net->depth[s], pool, seed) > kLdsDynamicMax)
+    const size_t lds = N == 64 ? nk::stage64_lds_bytes(net->depth[s]) : nk::stage_lds_bytes(N, net->depth[s], pool, seed);
+    if (lds > kLdsDynamicMax)
       return fail(NK_EUNSUPPORTED, "stage %d needs more than 160 KiB of LDS", s);
   }
   return NK_OK;
@@ -547,7 +554,9 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
       char nm[48];
       snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", s + 1, net.hw >> s);
       ProfScope ps(nm, stream);
-      if (nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream)) return hip_fail("stage kernel");
+      const int rc = (net.hw >> s) == 64 ? nk::launch_stage64(a, net.sb2 != 0.f, stream)
+                                         : nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream);
+      if (rc) return hip_fail("stage kernel");
     }
   }
   return NK_OK;
@@ -805,9 +814,10 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2) {
     }
     case NK_OP_MYRTLE: {
       NetDesc net;
-      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net)) return 0;
+      if (check_myrtle(static_cast<const nk_myrtle_cfg*>(cfg), &net, true)) return 0;
       const int64_t np = std::max<int64_t>(1, nk::pair_count(n1, n2, 0));
-      return plan_myrtle(net, n1, n2, false, std::min(np, kDefaultChunk)).total + 256 * NK_MAX_STAGES;
+      return plan_myrtle(net, n1, n2, false, std::min(np, net.hw > 32 ? kDefaultChunk64 : kDefaultChunk)).total +
+             256 * NK_MAX_STAGES;
     }
     case NK_OP_MYRTLE_BWD: {
       NetDesc net;
@@ -886,7 +896,7 @@ int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const n
 int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K,
                    int64_t ldk, void* ws, size_t ws_bytes, void* stream) {
   NetDesc net;
-  int rc = check_myrtle(cfg, &net);
+  int rc = check_myrtle(cfg, &net, true);
   if (rc) return rc;
   if (!x1 || !x2 || !K) return fail(NK_EINVAL, "null pointer argument");
   if (n1 <= 0 || n2 <= 0) return fail(NK_EINVAL, "n1 and n2 must be positive");

@@ -107,6 +107,9 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
                    int64_t max_blocks, hipStream_t stream);
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
+// first stage at 64x64 (seed, D <= 2 layers, pool; plain blocks only)
+size_t stage64_lds_bytes(int D);
+int launch_stage64(const StageArgs& a, bool bias, hipStream_t s);
 size_t stage_ntk_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage_ntk(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
 int prime_stage(int N, int D, bool seed, bool pool, bool bias);  // kernel attributes, no launch

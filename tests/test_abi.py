@@ -38,7 +38,9 @@ def test_workspace_size_queries():
 
 @pytest.mark.parametrize("kw,code", [
     (dict(hw=12), _lib.NK_EUNSUPPORTED),           # not a power of two
-    (dict(hw=64), _lib.NK_EUNSUPPORTED),           # above the tiled sizes
+    (dict(hw=128), _lib.NK_EUNSUPPORTED),          # above the supported sizes
+    (dict(hw=64, depth=(3, 1, 1)), _lib.NK_EUNSUPPORTED),  # 64x64 first stage with 3 layers
+    (dict(hw=64, depth=(2,)), _lib.NK_EUNSUPPORTED),  # 64x64 single stage (no pool)
     (dict(c=5), _lib.NK_EUNSUPPORTED),             # > 4 channels
     (dict(depth=(0, 1, 1)), _lib.NK_EUNSUPPORTED),  # first stage without a conv
     (dict(depth=(1, 1, 1, 1, 1)), None),           # too many stages (python side)
@@ -69,6 +71,29 @@ def test_depth4_first_stage_fits_below_32():
     assert L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 8, 8) > 0
     cfg = _cfg(hw=32, depth=(4, 1, 1))
     assert L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 8, 8) == 0
+
+
+def test_64x64_only_for_the_nngp_block():
+    """64x64 inputs: accepted by the NNGP block and its workspace query,
+    refused by the tangent kernel, the adjoint and the batched pass."""
+    L = _lib.lib()
+    cfg = _cfg(hw=64, depth=(2, 2, 2))
+    need = L.nk_workspace_size(_lib.NK_OP_MYRTLE, ctypes.byref(cfg), 256, 256)
+    assert need > 1024 * (32 ** 4 + 16 ** 4) * 4  # 1024 pairs per pass: their pooled stage inputs
+    assert L.nk_workspace_size(_lib.NK_OP_MYRTLE_NTK, ctypes.byref(cfg), 8, 8) == 0
+    assert L.nk_workspace_size(_lib.NK_OP_MYRTLE_BWD, ctypes.byref(cfg), 8, 8) == 0
+    p = ctypes.c_void_p(256)
+    # a valid 64x64 call that stops at the workspace check (no device work)
+    assert L.nk_myrtle_nngp(p, 4, p, 4, ctypes.byref(cfg), p, 4, p, 16, None) == _lib.NK_EINVAL
+    assert "workspace" in L.nk_last_error().decode()
+    assert L.nk_myrtle_ntk(p, 4, p, 4, ctypes.byref(cfg), p, p, 4, p, 1 << 30, None) == _lib.NK_EUNSUPPORTED
+    assert L.nk_myrtle_nngp_backward(p, 4, p, 4, ctypes.byref(cfg), p, 4, p, p, p, p, 1 << 30,
+                                     None) == _lib.NK_EUNSUPPORTED
+    tiles = (_lib.Tile * 1)()
+    tiles[0].x1 = tiles[0].x2 = tiles[0].K = 256
+    tiles[0].n1, tiles[0].n2, tiles[0].ldk = 5, 7, 7
+    assert L.nk_myrtle_nngp_batched_workspace(tiles, 1, ctypes.byref(cfg)) == 0
+    assert L.nk_myrtle_nngp_batched(tiles, 1, ctypes.byref(cfg), p, 1 << 30, None, 0) == _lib.NK_EUNSUPPORTED
 
 
 def test_myrtle_argument_validation():

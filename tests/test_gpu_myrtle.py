@@ -156,3 +156,48 @@ def test_myrtle10_32x32_block4096_sampled(nk):
     _say(f"  normalised error {err:.3e}")
     assert err <= TOL
     assert np.all(np.isfinite(kg)) and np.all(kg > 0)
+
+
+@pytest.mark.parametrize("n1,n2,depth,sb2", [(3, 4, (2, 2, 2), 0.0), (3, None, (2, 2, 2), 0.0),
+                                             (2, 3, (1, 2, 1), 0.1), (2, 2, (2, 1), 0.0)])
+def test_myrtle_64x64_blocks(nk, n1, n2, depth, sb2):
+    """64x64 inputs (their own first-stage kernel: a pair per workgroup, tile
+    columns in groups, the x part of the pool carried across groups): small
+    blocks against the oracle, symmetric and not, one and two first-stage
+    layers, with bias, and a two-stage network (64 -> 32, global pool)."""
+    x1 = synth.correlated_images(n1, 64, 64, 3, 6.0, 4004)
+    x2 = None if n2 is None else synth.correlated_images(n2, 64, 64, 3, 6.0, 4005)
+    kg, _ = _check_block(nk, x1, x2, depth, 2.0, sb2)
+    if x2 is None:
+        assert np.array_equal(kg, kg.T)
+
+
+def test_myrtle7_64x64_block256_sampled(nk):
+    """The 256 x 256 Myrtle-7 block on 64x64x3 correlated images (length scale
+    6 px) of the uneven-tile workload, checked on seeded samples against the
+    oracle; repeated calls give the same bits."""
+    w = synth.WORKLOADS["myrtle7_uneven64"]
+    n, hw = w["big_n"], w["big_hw"]
+    x1 = synth.correlated_images(n, hw, hw, 3, w["big_length"], w["big_seeds"][0])
+    x2 = synth.correlated_images(n, hw, hw, 3, w["big_length"], w["big_seeds"][1])
+    _say("myrtle7 64x64 256 x 256 block on GPU")
+    g1, g2 = _gpu(x1), _gpu(x2)
+    kg = nk.myrtle_nngp(g1, g2, w["depth"], w["sigma_w2"], w["sigma_b2"]).cpu().numpy()
+    torch.cuda.synchronize()
+    again = nk.myrtle_nngp(g1, g2, w["depth"], w["sigma_w2"], w["sigma_b2"]).cpu().numpy()
+    assert np.array_equal(kg, again)
+    rng = np.random.default_rng(4006)
+    pairs = np.concatenate([rng.integers(0, n, size=(10, 2)), np.array([[0, 0], [n - 1, n - 1], [0, n - 1]])])
+    net = oracle.Myrtle(w["depth"], w["sigma_w2"], w["sigma_b2"])
+    _say("oracle on sampled pairs")
+    kr = oracle.myrtle_pairs(x1, x2, pairs, net)
+    ua = np.unique(pairs[:, 0])
+    ub = np.unique(pairs[:, 1])
+    _, da = oracle.myrtle_self(x1[ua], net)
+    _, db = oracle.myrtle_self(x2[ub], net)
+    d1 = dict(zip(ua, da))
+    d2 = dict(zip(ub, db))
+    err = max(abs(kg[a, b] - k) / np.sqrt(d1[a] * d2[b]) for (a, b), k in zip(pairs, kr))
+    _say(f"  normalised error {err:.3e}")
+    assert err <= TOL
+    assert np.all(np.isfinite(kg)) and np.all(kg > 0)
