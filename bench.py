@@ -51,6 +51,7 @@ def _args():
     p.add_argument("--no-pcg", action="store_true", help="skip the preconditioned-CG solve measurement")
     p.add_argument("--no-cv8", action="store_true", help="skip the CV8 NNGP measurement")
     p.add_argument("--no-approx", action="store_true", help="skip the approximate-solver measurement")
+    p.add_argument("--no-64", action="store_true", help="skip the 64x64 Myrtle-7 block")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -172,6 +173,43 @@ def _ntk(torch, n: int = 1024):
     return {"value": round(n * n / dt, 3), "unit": "pairs/s", "pairs": n * n, "ms": round(dt * 1e3, 3),
             "workload": f"Myrtle-10 NTK and NNGP together, 32x32x3, one {n}x{n} block of the headline images",
             "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()}}
+
+
+def _myrtle64(torch):
+    """The 256 x 256 Myrtle-7 block on 64x64x3 images (length scale 6 px) of the
+    uneven-tile workload: one untimed and one timed call; the 64x64 first-stage
+    kernel's ALU roofline under the op model."""
+    import synth
+    from paper_2303_05420_amd import _lib, ops, workmodel
+
+    w = synth.WORKLOADS["myrtle7_uneven64"]
+    n, hw, depth = w["big_n"], w["big_hw"], w["depth"]
+    x1 = torch.from_numpy(synth.correlated_images(n, hw, hw, 3, w["big_length"], w["big_seeds"][0])).cuda()
+    x2 = torch.from_numpy(synth.correlated_images(n, hw, hw, 3, w["big_length"], w["big_seeds"][1])).cuda()
+    out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    ops.myrtle_nngp(x1, x2, depth, w["sigma_w2"], w["sigma_b2"], out=out)
+    torch.cuda.synchronize()
+    _lib.profile_read(reset=True)
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    ops.myrtle_nngp(x1, x2, depth, w["sigma_w2"], w["sigma_b2"], out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _lib.profile_enable(False)
+    prof = _lib.profile_read(reset=True)
+    launches, kms = prof[f"myrtle_stage1_n{hw}"]
+    flop_pair = (workmodel.FLOPS_PER_ENTRY_LAYER * depth[0] * hw ** 4
+                 + workmodel.FLOPS_PER_SEED_ENTRY_PER_CHANNEL * 3 * hw ** 4
+                 + workmodel.FLOPS_PER_POOLED_ENTRY * hw ** 4)
+    achieved = flop_pair * n * n / (kms / 1e3) / 1e12
+    print(f"myrtle7 64x64: {dt * 1e3:.1f} ms for {n * n} pairs", file=sys.stderr, flush=True)
+    return {"workload": f"Myrtle-7 NNGP, 64x64x3 correlated images (length scale 6 px), one {n}x{n} block",
+            "value": round(n * n / dt, 1), "unit": "entries/s", "ms": round(dt * 1e3, 3),
+            "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                         "kernel": f"myrtle_stage1_n{hw}", "avg_launch_ms": round(kms / launches, 3),
+                         "pairs_per_launch": n * n // launches}}
 
 
 def _batched(torch, full: bool):
@@ -546,6 +584,7 @@ def main():
     fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
     batched = None if a.no_batched else _batched(torch, a.batched_full)
     ntk = None if a.no_ntk else _ntk(torch)
+    m64 = None if a.no_64 else _myrtle64(torch)
     pcg = None if a.no_pcg else _pcg(torch, not a.no_cpu_baseline)
     cv8 = None if a.no_cv8 else _cv8(torch, not a.no_cpu_baseline)
     approx = None if a.no_approx else _approx(torch)
@@ -599,6 +638,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batched_tiles": batched,
         "ntk": ntk,
+        "myrtle7_64x64": m64,
         "fc3_gram": pcg.pop("fc_gram") if pcg else None,
         "pcg": pcg,
         "cv8": cv8,
