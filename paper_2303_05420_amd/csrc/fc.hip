@@ -5,8 +5,8 @@
 //   F(s, q, q') = sqrt(q q') / 2 J1(s / sqrt(q q'))
 //
 // The first layer's dot products are a dense (n1 x d) (d x n2) contraction:
-// they run on the fp32 matrix cores (v_mfma_f32_16x16x4_f32), and the ReLU
-// recursion is applied in the epilogue of the same kernel.  The diagonals
+// they run on the fp32 matrix cores (v_mfma_f32_16x16x4f32) from LDS tiles,
+// and the ReLU recursion is applied in the epilogue of the same kernel.  The diagonals
 // follow K_{l+1}(x, x) = sigma_w2 K_l(x, x) / 2 + sigma_b2 (F(q, q, q) = q/2).
 #include "nk_kernels.h"
 
@@ -38,46 +38,80 @@ __device__ __forceinline__ float4 load4_guard(const float* __restrict__ p, int64
   return make_float4(v[0], v[1], v[2], v[3]);
 }
 
-// 64 x 64 output tile per workgroup; each wave a 32 x 32 quadrant as 2 x 2
-// blocks of 16 x 16 MFMA.  Lane l feeds A[i = l % 16][k-slot l / 16] and
-// B[k-slot l / 16][j = l % 16]; each lane loads 4 consecutive k per k-slot
-// (a float4) and issues 4 MFMAs, so one iteration covers 16 k.
+// Tiling of the first-layer contraction.  A workgroup (4 waves) owns a
+// 128 x 128 output tile, each wave a 64 x 64 quadrant as 4 x 4 blocks of
+// 16 x 16 v_mfma_f32_16x16x4f32 accumulators (64 registers).  The k range
+// runs in tiles of FC_BK = 32: the 128 rows of x1 and of x2 for the tile sit
+// in LDS as [row][k] (row padded by 4 floats: 16-byte aligned rows, and the
+// 16 rows a block reads start on different banks); the next tile is loaded
+// into registers (4 + 4 float4 per thread) while the current one feeds the
+// MFMAs, and written to LDS between two barriers.  For a block, lane l feeds
+// A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16] of each 4-wide k step.
+constexpr int FC_BM = 128, FC_BK = 32, FC_LDR = FC_BK + 4;
+
 __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.y * 64 + 32 * (w >> 1);
-  const int64_t col0 = (int64_t)blockIdx.x * 64 + 32 * (w & 1);
+  __shared__ __attribute__((aligned(16))) float As[FC_BM * FC_LDR];
+  __shared__ __attribute__((aligned(16))) float Bs[FC_BM * FC_LDR];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * FC_BM, c0 = (int64_t)blockIdx.x * FC_BM;
+  const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   const int li = lane & 15, ks = lane >> 4;
   const bool vec = (a.d & 3) == 0;
-  floatx4 acc[2][2];
+  float4 pa[4], pb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int m = 0; m < 4; ++m) {
+      const int q = tid + 256 * m, row = q >> 3, kq = 4 * (q & 7);
+      pa[m] = load4_guard(a.x1, r0 + row, a.n1, a.d, k0 + kq, vec);
+      pb[m] = load4_guard(a.x2, c0 + row, a.n2, a.d, k0 + kq, vec);
+    }
+  };
+  auto store = [&]() {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < a.d; k0 += 16) {
-    float4 av[2], bv[2];
+    for (int m = 0; m < 4; ++m) {
+      const int q = tid + 256 * m, row = q >> 3, kq = 4 * (q & 7);
+      *reinterpret_cast<float4*>(&As[row * FC_LDR + kq]) = pa[m];
+      *reinterpret_cast<float4*>(&Bs[row * FC_LDR + kq]) = pb[m];
+    }
+  };
+  floatx4 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) av[i] = load4_guard(a.x1, row0 + 16 * i + li, a.n1, a.d, k0 + 4 * ks, vec);
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bv[j] = load4_guard(a.x2, col0 + 16 * j + li, a.n2, a.d, k0 + 4 * ks, vec);
+    for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < a.d; k0 += FC_BK) {
+    // (the last tile re-requests its own k range: in bounds, never stored)
+    fetch(k0 + FC_BK < a.d ? k0 + FC_BK : k0);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int kk = 0; kk < FC_BK; kk += 4) {
+      float av[4], bv[4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
-      }
+      for (int i = 0; i < 4; ++i) av[i] = As[(wr + 16 * i + li) * FC_LDR + kk + ks];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[(wc + 16 * j + li) * FC_LDR + kk + ks];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (k0 + FC_BK < a.d) {
+      __syncthreads();
+      store();
+      __syncthreads();
+    }
   }
   const float inv_d = 1.0f / (float)a.d;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t r = row0 + 16 * i + 4 * ks + v;
-        const int64_t c = col0 + 16 * j + li;
+        const int64_t r = r0 + wr + 16 * i + 4 * ks + v;
+        const int64_t c = c0 + wc + 16 * j + li;
         if (r >= a.n1 || c >= a.n2) continue;
         float k = a.sw2 * acc[i][j][v] * inv_d + a.sb2;
         float q1 = a.d1[r], q2 = a.d2[c];
@@ -105,7 +139,7 @@ int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream) {
   FcArgs b = a;
   b.d1 = d1;
   b.d2 = d2;
-  hipLaunchKernelGGL(fc_kernel, dim3((unsigned)((a.n2 + 63) / 64), (unsigned)((a.n1 + 63) / 64)), dim3(256), 0,
+  hipLaunchKernelGGL(fc_kernel, dim3((unsigned)((a.n2 + FC_BM - 1) / FC_BM), (unsigned)((a.n1 + FC_BM - 1) / FC_BM)), dim3(256), 0,
                      stream, b);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
