@@ -129,6 +129,35 @@ def test_myrtle_matches_matrix_form(hw, depth, sb2):
             assert abs(K[a, b] - ref) <= 1e-12 * abs(ref)
 
 
+@pytest.mark.parametrize("depth,sb2", [(1, 0.0), (3, 0.05), (2, 0.01)])
+def test_conv_reduces_to_fc_on_1x1_inputs(depth, sb2):
+    """On 1x1xC images a [3x3 SAME conv, ReLU] stack sees only its centre tap
+    (the eight others fall in the zero padding while the fan-in 9 C stays),
+    and the global pool over one pixel is the identity: the network is an FC
+    network with hidden weight variance sigma_w2 / 9 and readout variance
+    sigma_w2.  Composed here from the scalar ReLU map (itself pinned by
+    quadrature): K_1 = sw2/9 x.x'/C + sb2, K_{l+1} = sw2/9 F(K_l) + sb2,
+    K = sw2 F(K_D) + sb2."""
+    x = synth.iid_images(4, 1, 1, 5, 31)
+    net = oracle.Myrtle((depth,), 2.0, sb2)
+    K = oracle.myrtle_gram(x, None, net)
+    xf = x.reshape(4, -1).astype(np.float64)
+    c, sw2 = xf.shape[1], 2.0
+
+    def fc(a, b):
+        s = sw2 / 9 * (xf[a] @ xf[b]) / c + sb2
+        qa = sw2 / 9 * (xf[a] @ xf[a]) / c + sb2
+        qb = sw2 / 9 * (xf[b] @ xf[b]) / c + sb2
+        for layer in range(depth):
+            f, fa, fb = oracle.relu_map(s, qa, qb), oracle.relu_map(qa, qa, qa), oracle.relu_map(qb, qb, qb)
+            scale = sw2 / 9 if layer + 1 < depth else sw2
+            s, qa, qb = scale * f + sb2, scale * fa + sb2, scale * fb + sb2
+        return s
+
+    ref = np.array([[fc(a, b) for b in range(4)] for a in range(4)])
+    assert np.max(np.abs(K - ref) / np.abs(ref)) <= 1e-13
+
+
 def test_myrtle_nonsquare_matches_matrix_form():
     x = synth.iid_images(2, 4, 8, 2, 22)
     net = oracle.Myrtle((1, 1), 1.5, 0.02)
