@@ -501,8 +501,9 @@ def _pcg(torch, cpu: bool):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
-              "kernel blocks shard across GPUs without communication, see DESIGN.md.", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {a.gpus}); on several GPUs each would "
+              "compute its own Gram blocks with no communication, so the figure would be the one-GPU rate "
+              "times the GPU count.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
