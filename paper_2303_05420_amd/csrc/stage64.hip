@@ -109,7 +109,7 @@ __global__ __launch_bounds__(S64_THREADS) void stage64_kernel(const StageArgs ar
       // to what the output already holds
       const bool add_all = ky == 0;
       float A[N];
-      constexpr int SR = 4;  // seed rows whose pixels are requested together
+      constexpr int SR = 16;  // seed rows whose pixels are requested together
       // (an opaque offset keeps the 64 row addresses of each image from being
       // hoisted out of the sweep: they would pin 256 registers)
       const int z = opaque_zero();
