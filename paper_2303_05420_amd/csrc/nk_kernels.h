@@ -1,9 +1,31 @@
 // Kernel argument blocks and launchers shared between the HIP translation
 // units of libnk and its host API.
 #pragma once
+#include <atomic>
+
 #include "nk_common.h"
 
 namespace nk {
+
+// Dynamic LDS beyond 64 KiB has to be allowed per kernel, and per device.
+// `seen` is one kernel's record of the largest size already allowed on each
+// device (a zero-initialised static array of kMaxDevices in its launcher);
+// devices beyond kMaxDevices are set on every call.  Returns 0 or -3.
+constexpr int kMaxDevices = 64;
+inline int allow_dyn_lds(const void* fn, size_t lds, std::atomic<size_t>* seen) {
+  if (lds <= 64 * 1024) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -3;
+  std::atomic<size_t>* rec = (dev >= 0 && dev < kMaxDevices) ? &seen[dev] : nullptr;
+  if (rec && rec->load(std::memory_order_acquire) >= lds) return 0;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return -3;
+  if (rec) {
+    size_t cur = rec->load(std::memory_order_relaxed);
+    while (cur < lds && !rec->compare_exchange_weak(cur, lds, std::memory_order_acq_rel)) {
+    }
+  }
+  return 0;
+}
 
 struct PrepArgs {
   const float* x;     // images NHWC

@@ -204,12 +204,8 @@ template <int C, bool BIAS>
 static int launch_s64_t(const StageArgs& a, hipStream_t s) {
   auto fn = stage64_kernel<C, BIAS>;
   const size_t lds = stage64_lds_bytes(a.D);
-  static size_t attr_bytes = 0;  // per instantiation
-  if (attr_bytes < lds) {
-    if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-      return -3;
-    attr_bytes = lds;
-  }
+  static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
+  if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
   hipLaunchKernelGGL(fn, dim3((unsigned)a.np), dim3(S64_THREADS), lds, s, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

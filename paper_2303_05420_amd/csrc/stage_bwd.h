@@ -480,14 +480,8 @@ int launch_bwd_t(const StageBwdArgs& a, hipStream_t stream) {
   const int64_t nwg = (a.np + BCfg<N>::PPWG - 1) / BCfg<N>::PPWG;
   const size_t lds = (size_t)BCfg<N>::PPWG * bwd_slot_lds_bytes<N>(D, CC > 0);
   auto fn = stage_bwd_kernel<N, D, CC>;
-  if (lds > 64 * 1024) {
-    static size_t attr_bytes = 0;
-    if (attr_bytes < lds) {
-      if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -3;
-      attr_bytes = lds;
-    }
-  }
+  static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
+  if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
   hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(BCfg<N>::THREADS), lds, stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -426,19 +426,11 @@ __global__ __launch_bounds__((KCfg<N, NTK>::THREADS)) void stage_kernel(const St
   }  // units of this workgroup
 }
 
-// Launch of one instantiation (sets its LDS attribute first).
+// Allows one instantiation its dynamic LDS on the current device.
 template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
 int set_attr(size_t lds) {
-  auto fn = stage_kernel<N, SEED, POOL, BIAS, NTK>;
-  if (lds > 64 * 1024) {
-    static size_t attr_bytes = 0;  // per instantiation
-    if (attr_bytes < lds) {
-      if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -3;
-      attr_bytes = lds;
-    }
-  }
-  return 0;
+  static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
+  return allow_dyn_lds((const void*)stage_kernel<N, SEED, POOL, BIAS, NTK>, lds, seen);
 }
 
 template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
