@@ -152,9 +152,10 @@ def _fwd_bwd(torch):
 
 def _ntk(torch, n: int = 1024):
     """Myrtle-10 neural tangent kernel (with its NNGP) on an n x n block of the
-    headline images, timed once after an untimed 64 x 64 pass."""
+    headline images, timed once after an untimed 64 x 64 pass; the first-stage
+    kernel's ALU roofline under the tangent-kernel op model."""
     import synth
-    from paper_2303_05420_amd import _lib, ops
+    from paper_2303_05420_amd import _lib, ops, workmodel
 
     w = synth.WORKLOADS["myrtle10_32x32_4096"]
     x1 = torch.from_numpy(synth.correlated_images(n, 32, 32, 3, w["length"], w["seeds"][0])).cuda()
@@ -170,9 +171,16 @@ def _ntk(torch, n: int = 1024):
     _lib.profile_enable(False)
     prof = _lib.profile_read(reset=True)
     print(f"ntk: {dt:.2f} s for {n * n} pairs", file=sys.stderr, flush=True)
+    launches, kms = prof["myrtle_ntk_stage1_n32"]
+    flop_pair = workmodel.ntk_first_stage_flops_per_pair(32, 3, w["depth"][0])
+    achieved = flop_pair * n * n / (kms / 1e3) / 1e12
     return {"value": round(n * n / dt, 3), "unit": "pairs/s", "pairs": n * n, "ms": round(dt * 1e3, 3),
             "workload": f"Myrtle-10 NTK and NNGP together, 32x32x3, one {n}x{n} block of the headline images",
-            "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()}}
+            "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                         "kernel": "myrtle_ntk_stage1_n32", "avg_launch_ms": round(kms / launches, 3),
+                         "pairs_per_launch": n * n // launches, "flops_per_pair": flop_pair}}
 
 
 def _myrtle64(torch):

@@ -13,6 +13,14 @@ from typing import Sequence
 FLOPS_PER_ENTRY_LAYER = 30
 FLOPS_PER_SEED_ENTRY_PER_CHANNEL = 2
 FLOPS_PER_POOLED_ENTRY = 1
+# Tangent kernel (NTK), on top of the covariance's 30 per entry-layer: the box
+# sum of the tangent (6), the arc-cosine angle from the square root the map
+# already takes (a degree-6 polynomial and one product: 13) and the tangent
+# update, derivative factor times tangent plus covariance (2 FMA: 4).  The
+# network's first layer has no tangent input to sum (its tangent is its
+# covariance): 17 there.
+NTK_EXTRA_FLOPS_PER_ENTRY_LAYER = 23
+NTK_EXTRA_FLOPS_FIRST_LAYER = 17
 
 
 def stage_sizes(hw: int, n_stages: int):
@@ -47,3 +55,13 @@ def cv_flops_per_pair(hw: int, c: int, depth: int) -> int:
     layer, the seed's channel products, and the readout sum."""
     n2 = hw * hw
     return FLOPS_PER_ENTRY_LAYER * depth * n2 + FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c * n2 + FLOPS_PER_POOLED_ENTRY * n2
+
+
+def ntk_first_stage_flops_per_pair(hw: int, c: int, d: int) -> int:
+    """Op-model flops of the tangent kernel's first stage for one pair: seed,
+    d conv+ReLU layers of covariance and tangent at hw x hw, and the 2x2 pool
+    of both."""
+    n4 = hw ** 4
+    per_entry = (FLOPS_PER_ENTRY_LAYER * d + NTK_EXTRA_FLOPS_FIRST_LAYER
+                 + NTK_EXTRA_FLOPS_PER_ENTRY_LAYER * (d - 1))
+    return per_entry * n4 + FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c * n4 + 2 * FLOPS_PER_POOLED_ENTRY * n4

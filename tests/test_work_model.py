@@ -37,3 +37,14 @@ def test_myrtle10_counts():
     depth = [int(v) for v in g["myrtle10_conv_per_stage"].split(",")]
     assert workmodel.entry_layers_per_pair(32, depth) == 3 * (32 ** 4 + 16 ** 4 + 8 ** 4) == 3354624
     assert workmodel.entry_layers_per_pair(8, [2, 1, 1]) == 8464
+
+
+def test_ntk_first_stage_op_model():
+    # one layer at 2x2, one channel: 16 entries, 30 + 17 per entry-layer,
+    # 2 per seed entry and channel, 1 per pooled entry for each of the two
+    # pooled tiles
+    assert workmodel.ntk_first_stage_flops_per_pair(2, 1, 1) == 16 * (47 + 2 + 2)
+    # each further layer adds 30 + 23 per entry
+    d3 = workmodel.ntk_first_stage_flops_per_pair(32, 3, 3)
+    d2 = workmodel.ntk_first_stage_flops_per_pair(32, 3, 2)
+    assert d3 - d2 == 53 * 32 ** 4
