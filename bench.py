@@ -111,9 +111,10 @@ def _pcg_traffic(n: int):
 
 def _fwd_bwd(torch):
     """One timed forward + backward pass of the kernel-ridge-regression loss
-    through the Myrtle-5 NNGP (after one untimed pass)."""
+    through the Myrtle-5 NNGP (after one untimed pass); the ALU roofline of
+    the first stage's adjoint kernel under the adjoint op model."""
     import synth
-    from paper_2303_05420_amd import _lib, krr_grad
+    from paper_2303_05420_amd import _lib, krr_grad, workmodel
 
     w = synth.WORKLOADS["myrtle5_krr_grad"]
     ns, nt = w["n_support"], w["n_target"]
@@ -142,12 +143,18 @@ def _fwd_bwd(torch):
     fwd_ms = sum(v[1] for k, v in prof.items() if k.startswith("myrtle_stage") and not k.endswith("_bwd"))
     bwd_ms = sum(v[1] for k, v in prof.items() if k.endswith("_bwd"))
     print(f"fwd+bwd: {dt * 1e3:.1f} ms for {pairs} pairs", file=sys.stderr, flush=True)
+    launches, kms = prof["myrtle_stage1_n32_bwd"]
+    flop_pair = workmodel.adjoint_first_stage_flops_per_pair(32, 3, w["depth"][0])
+    achieved = flop_pair * pairs / (kms / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None, "kernel": "myrtle_stage1_n32_bwd",
+            "avg_launch_ms": round(kms / launches, 3), "launches": launches, "flops_per_pair": flop_pair}
     return {"value": round(pairs / dt, 3), "unit": "pairs/s", "pairs": pairs, "ms": round(dt * 1e3, 3),
             "workload": f"Myrtle-5 NNGP at 32x32x3, KRR of {ns} learnable support images onto {nt} targets "
                         f"(K_ss symmetric + K_ts), loss + d/d(support pixels) + d/d(sigma_w2, sigma_b2)",
             "loss": loss, "dsigma": [float(v) for v in ds.cpu().tolist()],
             "kernels_ms": {k: round(v[1], 3) for k, v in prof.items()},
-            "stage_kernels_fwd_ms": round(fwd_ms, 3), "stage_kernels_bwd_ms": round(bwd_ms, 3)}
+            "stage_kernels_fwd_ms": round(fwd_ms, 3), "stage_kernels_bwd_ms": round(bwd_ms, 3), "roofline": roof}
 
 
 def _ntk(torch, n: int = 1024):

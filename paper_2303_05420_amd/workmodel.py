@@ -21,6 +21,16 @@ FLOPS_PER_POOLED_ENTRY = 1
 # covariance): 17 there.
 NTK_EXTRA_FLOPS_PER_ENTRY_LAYER = 23
 NTK_EXTRA_FLOPS_FIRST_LAYER = 17
+# Adjoint, per entry and layer reversed, for the cotangent of one image of the
+# pair: the derivative of the map (the angle as above, 13, and 1 - angle, 1),
+# the cotangents of its argument and of the variance tables (rho_bar, v_bar
+# and w: 6), one table-adjoint sum (1), the two hyperparameter sums (3) and
+# the box of v_bar (6).  The seed's reverse is 2 flops per channel for one
+# image, the pool's 1 per entry.  Recomputation is not counted: the model is
+# one forward pass plus this.
+ADJ_FLOPS_PER_ENTRY_LAYER = 30
+ADJ_FLOPS_PER_SEED_ENTRY_PER_CHANNEL = 2
+ADJ_FLOPS_PER_POOLED_ENTRY = 1
 
 
 def stage_sizes(hw: int, n_stages: int):
@@ -65,3 +75,12 @@ def ntk_first_stage_flops_per_pair(hw: int, c: int, d: int) -> int:
     per_entry = (FLOPS_PER_ENTRY_LAYER * d + NTK_EXTRA_FLOPS_FIRST_LAYER
                  + NTK_EXTRA_FLOPS_PER_ENTRY_LAYER * (d - 1))
     return per_entry * n4 + FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c * n4 + 2 * FLOPS_PER_POOLED_ENTRY * n4
+
+
+def adjoint_first_stage_flops_per_pair(hw: int, c: int, d: int) -> int:
+    """Op-model flops of the first stage's adjoint for one pair: the forward
+    values of its d layers once (seed, layers, pool) and their reverse."""
+    n4 = hw ** 4
+    fwd = FLOPS_PER_ENTRY_LAYER * d + FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c + FLOPS_PER_POOLED_ENTRY
+    rev = ADJ_FLOPS_PER_ENTRY_LAYER * d + ADJ_FLOPS_PER_SEED_ENTRY_PER_CHANNEL * c + ADJ_FLOPS_PER_POOLED_ENTRY
+    return (fwd + rev) * n4

@@ -48,3 +48,11 @@ def test_ntk_first_stage_op_model():
     d3 = workmodel.ntk_first_stage_flops_per_pair(32, 3, 3)
     d2 = workmodel.ntk_first_stage_flops_per_pair(32, 3, 2)
     assert d3 - d2 == 53 * 32 ** 4
+
+
+def test_adjoint_first_stage_op_model():
+    # forward values (30 per layer, 2 per channel, 1 pooled) plus a reverse
+    # of the same size: twice the forward's first-stage count
+    for hw, c, d in ((2, 1, 1), (32, 3, 2), (16, 4, 3)):
+        fwd = (30 * d + 2 * c + 1) * hw ** 4
+        assert workmodel.adjoint_first_stage_flops_per_pair(hw, c, d) == 2 * fwd
