@@ -172,6 +172,15 @@ def test_myrtle_64x64_blocks(nk, n1, n2, depth, sb2):
         assert np.array_equal(kg, kg.T)
 
 
+@pytest.mark.parametrize("c,depth,sb2", [(1, (2, 2, 2), 0.0), (2, (1, 1), 0.05), (4, (2, 1, 1), 0.0)])
+def test_myrtle_64x64_channels(nk, c, depth, sb2):
+    """64x64 first stage with 1, 2 and 4 input channels (the kernel is
+    instantiated per channel count), 2 x 3 blocks against the oracle."""
+    x1 = synth.correlated_images(2, 64, 64, c, 6.0, 4100 + c)
+    x2 = synth.correlated_images(3, 64, 64, c, 6.0, 4110 + c)
+    _check_block(nk, x1, x2, depth, 2.0, sb2)
+
+
 def test_myrtle7_64x64_block256_sampled(nk):
     """The 256 x 256 Myrtle-7 block on 64x64x3 correlated images (length scale
     6 px) of the uneven-tile workload, checked on seeded samples against the
