@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -338,17 +339,19 @@ BatchPlan plan_batched(const NetDesc& net, int64_t rows, int64_t ntiles, int64_t
   return p;
 }
 
-int g_cu_count = 0;
-
+// Compute units of the current device (0 if unknown), queried once per device.
 int cu_count() {
-  if (g_cu_count <= 0) {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      return 0;
-    g_cu_count = n;
+  static std::atomic<int> counts[nk::kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < nk::kMaxDevices) {
+    const int c = counts[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
   }
-  return g_cu_count;
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 0;
+  if (dev < nk::kMaxDevices) counts[dev].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 // Stage passes of chunks [p_lo, p_hi) of a batched pass.
@@ -904,10 +907,18 @@ int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, con
   if (!ws) return fail(NK_EINVAL, "workspace is NULL");
   const bool sym = (x1 == x2) && (n1 == n2);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
-  const int64_t chunk = max_chunk(net, n1, n2, sym, ws_bytes, npairs);
+  int64_t chunk = max_chunk(net, n1, n2, sym, ws_bytes, npairs);
   if (chunk < 1) {
     return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
                 plan_myrtle(net, n1, n2, sym, 1).total + 256 * NK_MAX_STAGES);
+  }
+  if (net.hw > 32) {
+    // The 64x64 first stage runs one pair per workgroup and one workgroup per
+    // CU: passes of a whole number of CU rounds leave no partly filled last
+    // round, so a larger workspace does not lengthen them.
+    chunk = std::min(chunk, kDefaultChunk64);
+    const int cus = cu_count();
+    if (cus > 0 && chunk > cus) chunk -= chunk % cus;
   }
   const MyrtlePlan p = plan_myrtle(net, n1, n2, sym, chunk);
   hipStream_t s = (hipStream_t)stream;
