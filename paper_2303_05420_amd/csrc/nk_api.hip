@@ -912,11 +912,13 @@ int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, con
     return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
                 plan_myrtle(net, n1, n2, sym, 1).total + 256 * NK_MAX_STAGES);
   }
+  // Passes are not lengthened beyond the default by a larger workspace: the
+  // default fills whole rounds of resident workgroups, an arbitrary length
+  // leaves a partly filled last round.  The 64x64 first stage runs one pair
+  // per workgroup and one workgroup per CU: its passes are also rounded down
+  // to a multiple of the CU count.
+  chunk = std::min(chunk, net.hw > 32 ? kDefaultChunk64 : kDefaultChunk);
   if (net.hw > 32) {
-    // The 64x64 first stage runs one pair per workgroup and one workgroup per
-    // CU: passes of a whole number of CU rounds leave no partly filled last
-    // round, so a larger workspace does not lengthen them.
-    chunk = std::min(chunk, kDefaultChunk64);
     const int cus = cu_count();
     if (cus > 0 && chunk > cus) chunk -= chunk % cus;
   }
@@ -951,10 +953,11 @@ int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, cons
       return fail(NK_EUNSUPPORTED, "tangent-kernel stage %d needs more than 160 KiB of LDS", st);
   const bool sym = (x1 == x2) && (n1 == n2);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
-  const int64_t chunk = max_chunk_ntk(net, n1, n2, sym, ws_bytes, npairs);
+  int64_t chunk = max_chunk_ntk(net, n1, n2, sym, ws_bytes, npairs);
   if (chunk < 1)
     return fail(NK_EINVAL, "workspace too small (need at least %zu bytes)",
                 plan_ntk(net, n1, n2, sym, 1).total + 256 * NK_MAX_STAGES);
+  chunk = std::min(chunk, kDefaultChunk);  // whole rounds of workgroups, as for the NNGP
   const MyrtlePlan p = plan_ntk(net, n1, n2, sym, chunk);
   hipStream_t s = (hipStream_t)stream;
   float2* tab1 = at<float2>(ws, p.tab1);
