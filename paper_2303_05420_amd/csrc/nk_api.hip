@@ -63,7 +63,12 @@ struct ProfScope {
     }
     if (!on) return;
     rec.name = name;
-    if (hipEventCreate(&rec.start) != hipSuccess || hipEventCreate(&rec.stop) != hipSuccess) {
+    if (hipEventCreate(&rec.start) != hipSuccess) {
+      on = false;
+      return;
+    }
+    if (hipEventCreate(&rec.stop) != hipSuccess) {
+      hipEventDestroy(rec.start);
       on = false;
       return;
     }
