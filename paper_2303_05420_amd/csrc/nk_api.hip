@@ -132,7 +132,7 @@ int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net, bool allow64 = false) {
     const int N = net->hw >> s;
     const bool seed = s == 0, pool = s + 1 < net->S;
     // 160 KiB per workgroup, less 1 KiB for the kernels' static LDS
-    const size_t lds = N == 64 ? nk::stage64_lds_bytes(net->depth[s]) : nk::stage_lds_bytes(N, net->depth[s], pool, seed);
+    const size_t lds = N == 64 ? nk::stage64_lds_bytes(net->depth[s], net->C) : nk::stage_lds_bytes(N, net->depth[s], pool, seed);
     if (lds > kLdsDynamicMax)
       return fail(NK_EUNSUPPORTED, "stage %d needs more than 160 KiB of LDS", s);
   }

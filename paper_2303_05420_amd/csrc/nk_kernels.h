@@ -130,7 +130,7 @@ int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, d
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
 // first stage at 64x64 (seed, D <= 2 layers, pool; plain blocks only)
-size_t stage64_lds_bytes(int D);
+size_t stage64_lds_bytes(int D, int C);
 int launch_stage64(const StageArgs& a, bool bias, hipStream_t s);
 size_t stage_ntk_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage_ntk(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);

@@ -35,6 +35,11 @@ namespace nk {
 
 constexpr int S64_THREADS = 512;  // 8 waves, one tile column each
 
+// Rows of the first image kept in LDS (channel-major per row, lane-contiguous
+// reads) for the first batch of seed rows: what fits beside the tables and
+// the pooling row at depth 2 (12 KiB at 3 channels); none at 4 channels.
+__host__ __device__ constexpr int s64_x1_rows(int C) { return C <= 3 ? 16 : 0; }
+
 // [3x3 conv, ReLU] on one 64-row tile; as tile_layer, with the second
 // image's table rows wrapping: row r of tile (ky, kx) reads pixel row
 // (r + ky) mod 64 of x2.
@@ -70,6 +75,8 @@ __global__ __launch_bounds__(S64_THREADS) void stage64_kernel(const StageArgs ar
   float2* t1 = reinterpret_cast<float2*>(smem);
   float2* t2 = t1 + D * NN;
   float* red = reinterpret_cast<float*>(t2 + D * NN);  // [4][H][H]: one coarse row of the group's 4 columns
+  constexpr int XR = s64_x1_rows(C);
+  float* x1l = red + 4 * H2;  // [XR][C][N]: the first XR rows of the first image
   const int tid = threadIdx.x, w = tid >> 6, ix = tid & 63;
 
   const int64_t pl = xcd_logical_block();
@@ -79,6 +86,10 @@ __global__ __launch_bounds__(S64_THREADS) void stage64_kernel(const StageArgs ar
   for (int e = tid; e < D * NN; e += S64_THREADS) {
     t1[e] = args.tab1[ia * args.tablen + args.taboff + e];
     t2[e] = args.tab2[ib * args.tablen + args.taboff + e];
+  }
+  for (int e = tid; e < XR * N * C; e += S64_THREADS) {
+    const int row = e / (N * C), col = (e / C) % N, c = e % C;  // e = (row N + col) C + c
+    x1l[(row * C + c) * N + col] = args.x1[ia * NN * C + e];
   }
   __syncthreads();
   const float* x1p = args.x1 + (ia * NN + ix) * C;
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(S64_THREADS) void stage64_kernel(const StageArgs ar
           const float* p2 = x2s + ((r0 + k + ky) & (N - 1)) * N * C;
 #pragma unroll
           for (int c = 0; c < C; ++c) {
-            u[k][c] = p1[c];
+            u[k][c] = r0 + k < XR ? x1l[((r0 + k) * C + c) * N + ix] : p1[c];
             v[k][c] = p2[c];
           }
         }
@@ -198,12 +209,15 @@ __global__ __launch_bounds__(S64_THREADS) void stage64_kernel(const StageArgs ar
   }
 }
 
-size_t stage64_lds_bytes(int D) { return (size_t)2 * D * 64 * 64 * sizeof(float2) + (size_t)4 * 32 * 32 * sizeof(float); }
+size_t stage64_lds_bytes(int D, int C) {
+  return (size_t)2 * D * 64 * 64 * sizeof(float2) + (size_t)4 * 32 * 32 * sizeof(float) +
+         (size_t)s64_x1_rows(C) * C * 64 * sizeof(float);
+}
 
 template <int C, bool BIAS>
 static int launch_s64_t(const StageArgs& a, hipStream_t s) {
   auto fn = stage64_kernel<C, BIAS>;
-  const size_t lds = stage64_lds_bytes(a.D);
+  const size_t lds = stage64_lds_bytes(a.D, C);
   static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
   if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
   hipLaunchKernelGGL(fn, dim3((unsigned)a.np), dim3(S64_THREADS), lds, s, a);
