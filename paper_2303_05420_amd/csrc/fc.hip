@@ -48,12 +48,29 @@ __device__ __forceinline__ float4 load4_guard(const float* __restrict__ p, int64
 // MFMAs, and written to LDS between two barriers.  For a block, lane l feeds
 // A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16] of each 4-wide k step.
 constexpr int FC_BM = 128, FC_BK = 32, FC_LDR = FC_BK + 4;
+// Tile order.  Workgroups go to the 8 XCDs round-robin in launch order and
+// each XCD has its own L2, so the launch index is first mapped to one
+// contiguous range of tiles per XCD; each range walks the output in groups
+// of FC_GROUP tile rows, column by column, so that the tiles an XCD runs at
+// the same time share few x1 row tiles and x2 column tiles.
+constexpr int FC_GROUP = 8;
 
 __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
   __shared__ __attribute__((aligned(16))) float As[FC_BM * FC_LDR];
   __shared__ __attribute__((aligned(16))) float Bs[FC_BM * FC_LDR];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t r0 = (int64_t)blockIdx.y * FC_BM, c0 = (int64_t)blockIdx.x * FC_BM;
+  int64_t r0, c0;
+  {
+    const int64_t gx = gridDim.x, gy = gridDim.y, nb = gx * gy;
+    const int64_t lin = (int64_t)blockIdx.y * gx + blockIdx.x;
+    const int64_t xcd = lin & 7, q = nb >> 3, rem = nb & 7;
+    const int64_t id = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + (lin >> 3);
+    const int64_t grp = id / (FC_GROUP * gx), first = grp * FC_GROUP;
+    const int64_t rows = gy - first < FC_GROUP ? gy - first : FC_GROUP;
+    const int64_t in = id - first * gx;
+    r0 = (first + in % rows) * FC_BM;
+    c0 = (in / rows) * FC_BM;
+  }
   const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   const int li = lane & 15, ks = lane >> 4;
   const bool vec = (a.d & 3) == 0;
