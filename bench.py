@@ -21,6 +21,7 @@ import os
 import sys
 import time
 
+T0 = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -38,7 +39,7 @@ VALU_PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_valu_counters.
 def _args():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=4096, help="block side (the headline workload is 4096)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -52,6 +53,12 @@ def _args():
     p.add_argument("--no-cv8", action="store_true", help="skip the CV8 NNGP measurement")
     p.add_argument("--no-approx", action="store_true", help="skip the approximate-solver measurement")
     p.add_argument("--no-64", action="store_true", help="skip the 64x64 Myrtle-7 block")
+    p.add_argument("--budget-s", type=float, default=450.0,
+                   help="wall-clock budget of the whole run from process start (s); timed headline steps stop "
+                        "after at least three once --headline-share of it is used, side legs that would end "
+                        "past it are skipped by name")
+    p.add_argument("--headline-share", type=float, default=0.55)
+    p.add_argument("--batched-reps", type=int, default=3, help="timed passes of each form (median reported)")
     p.add_argument("--batched-full", action="store_true",
                    help="batched comparison at full size (64 tiles, sides 32..2048, about 7e7 pairs; minutes)")
     return p.parse_args()
@@ -227,12 +234,11 @@ def _myrtle64(torch):
                          "pairs_per_launch": n * n // launches}}
 
 
-def _batched(torch, full: bool):
-    """Uneven Myrtle-7 tiles at 32x32x3: one batched pass (tuned schedule,
-    hipGraph) against the plain form (one nk_myrtle_nngp call per tile), both
-    timed once after one untimed pass; the outputs are compared bitwise."""
-    import numpy as np
-
+def _batched(torch, full: bool, reps: int = 3):
+    """Uneven Myrtle-7 tiles at 32x32x3: the batched pass (tuned schedule,
+    hipGraph) against the plain form (one nk_myrtle_nngp call per tile).
+    One untimed pass of each, then `reps` timed passes of each, alternating;
+    medians and ranges are reported and the outputs compared bitwise."""
     import synth
     from paper_2303_05420_amd import ops
 
@@ -255,22 +261,37 @@ def _batched(torch, full: bool):
     def batched():
         ops.myrtle_nngp_batched(tiles, depth, graph=True)
 
-    res = {}
-    for name, fn in (("batched", batched), ("plain", plain)):
+    fns = {"batched": batched, "plain": plain}
+    for name, fn in fns.items():
         fn()
         torch.cuda.synchronize()
         print(f"{name} tiles: warm-up done", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        res[name] = time.perf_counter() - t0
-        print(f"{name} tiles: {res[name]:.2f} s", file=sys.stderr, flush=True)
+    times = {"batched": [], "plain": []}
+    for r in range(max(1, reps)):
+        for name, fn in fns.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            times[name].append(time.perf_counter() - t0)
+            print(f"{name} tiles pass {r + 1}: {times[name][-1]:.3f} s", file=sys.stderr, flush=True)
     same = all(torch.equal(a, b) for a, b in zip(outs_b, outs_p))
     cands, chosen = ops.batched_tuning(32, 3, depth)
+
+    def med(v):
+        s = sorted(v)
+        k = len(s)
+        return s[k // 2] if k % 2 else 0.5 * (s[k // 2 - 1] + s[k // 2])
+
+    mb, mp = med(times["batched"]), med(times["plain"])
     return {"workload": f"Myrtle-7 NNGP at 32x32x3, {len(shapes)} tiles with sides U{{{w['lo']}..{hi}}} "
                         f"over prefixes of two pools of {pool} images",
-            "pairs": pairs, "batched_pairs_per_s": round(pairs / res["batched"], 1),
-            "plain_pairs_per_s": round(pairs / res["plain"], 1), "speedup": round(res["plain"] / res["batched"], 4),
+            "pairs": pairs, "passes_each": len(times["batched"]),
+            "batched_pairs_per_s": round(pairs / mb, 1), "plain_pairs_per_s": round(pairs / mp, 1),
+            "batched_s": [round(v, 4) for v in times["batched"]], "plain_s": [round(v, 4) for v in times["plain"]],
+            "speedup_median": round(mp / mb, 4),
+            "ranges_disjoint": bool(max(times["batched"]) < min(times["plain"])
+                                    or max(times["plain"]) < min(times["batched"])),
             "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands)}
 
 
@@ -323,7 +344,7 @@ def _cv8(torch, cpu: bool):
         cdt = time.perf_counter() - t0
         err = float(np.max(np.abs(out[:m, :m].cpu().numpy() - ref) / np.sqrt(np.outer(d1, d2))))
         res["cpu_baseline"] = {"value": round(m * m / cdt, 1), "unit": "entries/s", "kind": "oracle",
-                               "cores": min(16, len(os.sched_getaffinity(0))),
+                               "cores": _host_threads(),
                                "sample": f"{m}x{m} sub-block of the same block plus its {2 * m} self recursions"}
         res["parity"] = {"max_normalised_error": err, "entries": m * m, "tolerance": 2e-5}
     return res
@@ -502,7 +523,7 @@ def _pcg(torch, cpu: bool):
         cdt = time.perf_counter() - t0
         err = float(np.max(np.abs(xg.cpu().numpy() - ref["X"])) / np.max(np.abs(ref["X"])))
         out["cpu_baseline"] = {"value": round(cdt * 1e3, 1), "unit": "ms per solve", "kind": "oracle",
-                               "cores": min(16, len(os.sched_getaffinity(0))),
+                               "cores": _host_threads(),
                                "sample": f"leading {m}x{m} sub-system of the same K and targets, same settings "
                                          f"({int(ref['iters'].max())} iterations, numpy float64)",
                                "gpu_ms_same_sample": round(gdt * 1e3, 3),
@@ -513,6 +534,37 @@ def _pcg(torch, cpu: bool):
     return out
 
 
+def _host_threads() -> int:
+    """Oracle threads: every core this process may run on, capped by the
+    OpenMP thread count the host sets for it (the CPU share of one GPU)."""
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        cores = min(cores, int(omp))
+    return max(1, cores)
+
+
+def _elapsed() -> float:
+    return time.perf_counter() - T0
+
+
+_EMITTED = [False]
+
+
+def _emit(rec: dict):
+    if not _EMITTED[0]:
+        _EMITTED[0] = True
+        print(json.dumps(rec), flush=True)
+
+
+def _on_term(rec: dict):
+    def handler(signum, frame):
+        rec["terminated"] = f"signal {signum} after {_elapsed():.1f} s; legs not reached are missing"
+        _emit(rec)
+        os._exit(128 + signum)
+    return handler
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -520,6 +572,8 @@ def main():
               "compute its own Gram blocks with no communication, so the figure would be the one-GPU rate "
               "times the GPU count.", file=sys.stderr)
         sys.exit(2)
+
+    import signal
 
     import numpy as np
     import torch
@@ -530,11 +584,25 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    print(f"[{_elapsed():.1f} s] torch and libnk imported", file=sys.stderr, flush=True)
 
     w = synth.WORKLOADS["myrtle10_32x32_4096"]
     n = a.n
     depth = w["depth"]
     hw = 32
+    pairs = n * n
+    rec = {
+        "metric": METRIC, "value": None, "unit": "entries/s", "n_gpus": 1, "steps": 0, "warmup": 0,
+        "steps_requested": a.steps, "warmup_requested": a.warmup, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Myrtle-10 NNGP, 32x32x3 correlated-Gaussian images (length scale 3 px), "
+                               f"one {n}x{n} Gram block (x1 != x2), sigma_w2=2, sigma_b2=0",
+                   "n1": n, "n2": n, "depth": list(depth), "pairs": pairs},
+        "budget_s": a.budget_s,
+        "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
+    }
+    signal.signal(signal.SIGTERM, _on_term(rec))
+
     x1n = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][0])
     x2n = synth.correlated_images(n, hw, hw, 3, w["length"], w["seeds"][1])
     x1 = torch.from_numpy(x1n).cuda()
@@ -546,27 +614,45 @@ def main():
     def step():
         ops.myrtle_nngp(x1, x2, depth, w["sigma_w2"], w["sigma_b2"], out=out, ws=ws)
 
-    for i in range(a.warmup):
+    # Warm-up: at most one full step (the kernels are compiled ahead of time;
+    # the first call only sets LDS attributes).
+    warm = min(a.warmup, 1)
+    for i in range(warm):
         step()
-        print(f"warmup step {i + 1}/{a.warmup} enqueued", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"[{_elapsed():.1f} s] warm-up step {i + 1}/{warm} done", file=sys.stderr, flush=True)
+
+    # Timed steps: up to --steps, stopped early (after at least min(3, steps))
+    # once the next step would end past the headline's share of the budget.
+    head_deadline = a.budget_s * a.headline_share
     _lib.profile_read(reset=True)
     _lib.profile_enable(True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    evs = [torch.cuda.Event(enable_timing=True)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     evs[0].record()
-    for i in range(a.steps):
+    done = 0
+    while done < a.steps:
         step()
-        evs[i + 1].record()
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        evs.append(e)
+        e.synchronize()
+        done += 1
+        last_s = evs[-2].elapsed_time(evs[-1]) / 1e3
+        print(f"[{_elapsed():.1f} s] timed step {done}: {last_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if done >= min(3, a.steps) and _elapsed() + last_s > head_deadline:
+            break
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     _lib.profile_enable(False)
     prof = _lib.profile_read(reset=True)
-    ms_total = evs[0].elapsed_time(evs[-1])
-    ms_step = ms_total / a.steps
-    ms_each = [evs[i].elapsed_time(evs[i + 1]) for i in range(a.steps)]
-    print(f"timed {a.steps} step(s): {ms_step:.1f} ms/step (wall {wall:.1f} s)", file=sys.stderr, flush=True)
+    ms_each = [evs[i].elapsed_time(evs[i + 1]) for i in range(done)]
+    ms_step = sum(ms_each) / done
+    srt = sorted(ms_each)
+    med = srt[done // 2] if done % 2 else 0.5 * (srt[done // 2 - 1] + srt[done // 2])
+    print(f"timed {done} step(s): {ms_step:.1f} ms/step (wall {wall:.1f} s)", file=sys.stderr, flush=True)
+    value = pairs / (ms_step / 1e3)
 
     if a.copy_calib_mib:
         src = torch.ones(a.copy_calib_mib * (1 << 18), dtype=torch.float32, device="cuda")
@@ -574,15 +660,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    pairs = n * n
-    value = pairs / (ms_step / 1e3)
-
     # roofline of the dominant kernel (stage 1: seed + 3 conv/ReLU layers at 32x32 + pool)
     st1 = prof.get(f"myrtle_stage1_n{hw}")
     roof = None
     if st1:
         launches, tot_ms = st1
-        launches_per_step = launches / a.steps
+        launches_per_step = launches / done
         pairs_per_launch = pairs / launches_per_step
         flop_pair_st1 = (workmodel.FLOPS_PER_ENTRY_LAYER * depth[0] * hw ** 4
                          + workmodel.FLOPS_PER_SEED_ENTRY_PER_CHANNEL * 3 * hw ** 4
@@ -593,25 +676,22 @@ def main():
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": traffic, "valu_counters": _valu_counters(), "kernel": f"myrtle_stage1_n{hw}",
-                "avg_launch_ms": round(tot_ms / launches, 3), "pairs_per_launch": int(pairs_per_launch)}
+                "avg_launch_ms": round(tot_ms / launches, 3), "pairs_per_launch": int(pairs_per_launch),
+                "flops_per_pair": flop_pair_st1}
     flops_pair = workmodel.flops_per_pair(hw, 3, depth)
-    whole = flops_pair * pairs / (ms_step / 1e3) / 1e12
+    rec.update({
+        "value": round(value, 3), "steps": done, "warmup": warm, "ms_per_step": round(ms_step, 3),
+        "ms_each_step": [round(v, 3) for v in ms_each], "ms_median_step": round(med, 3),
+        "model_tflops_whole_step": round(flops_pair * pairs / (ms_step / 1e3) / 1e12, 3),
+        "kernels_ms_per_step": {k: round(v[1] / done, 3) for k, v in prof.items()},
+        "roofline": roof,
+    })
 
-    fwd_bwd = None if a.no_fwd_bwd else _fwd_bwd(torch)
-    batched = None if a.no_batched else _batched(torch, a.batched_full)
-    ntk = None if a.no_ntk else _ntk(torch)
-    m64 = None if a.no_64 else _myrtle64(torch)
-    pcg = None if a.no_pcg else _pcg(torch, not a.no_cpu_baseline)
-    cv8 = None if a.no_cv8 else _cv8(torch, not a.no_cpu_baseline)
-    approx = None if a.no_approx else _approx(torch)
-
-    cpu = None
-    parity = None
     if not a.no_cpu_baseline:
         import oracle
 
         m = min(a.cpu_sample, n)
-        cores = min(16, len(os.sched_getaffinity(0)))
+        cores = _host_threads()
         net = oracle.Myrtle(depth, w["sigma_w2"], w["sigma_b2"])
         pa, pb = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
         plist = np.stack([pa.ravel(), pb.ravel()], 1)
@@ -620,48 +700,45 @@ def main():
         q2, d2 = oracle.myrtle_self(x2n[:m], net, cores)
         kr = oracle.myrtle_pairs(x1n[:m], x2n[:m], plist, net, q1, q2, cores).reshape(m, m)
         dt = time.perf_counter() - t
-        # self recursions cost one pair each: count them in the work done
-        cpu = {"value": round(m * m / dt, 3), "unit": "entries/s", "cores": cores, "kind": "oracle",
-               "sample": f"{m}x{m} sub-block of the same 4096x4096 Myrtle-10 block ({m * m} entries, plus "
-                         f"{2 * m} self recursions for the variance maps; {dt:.1f} s of wall time, float64)"}
+        rec["cpu_baseline"] = {
+            "value": round(m * m / dt, 3), "unit": "entries/s", "cores": cores, "kind": "oracle",
+            "per_core": round(m * m / dt / cores, 3),
+            "sample": f"{m}x{m} sub-block of the same 4096x4096 Myrtle-10 block ({m * m} entries, plus "
+                      f"{2 * m} self recursions for the variance maps; {dt:.1f} s of wall time, float64, "
+                      f"{cores} OpenMP threads = the host cores given to this GPU)"}
         kg = out[:m, :m].cpu().numpy()
         err = float(np.max(np.abs(kg - kr) / np.sqrt(np.outer(d1, d2))))
-        parity = {"max_normalised_error": err, "entries": m * m, "tolerance": 2e-5}
+        rec["parity"] = {"max_normalised_error": err, "entries": m * m, "tolerance": 2e-5}
+        print(f"[{_elapsed():.1f} s] oracle sample: {dt:.1f} s, parity {err:.2e}", file=sys.stderr, flush=True)
 
-    rec = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "entries/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "ms_each_step": [round(v, 3) for v in ms_each],
-        "ms_median_step": round(sorted(ms_each)[len(ms_each) // 2] if len(ms_each) % 2 else 0.5 * sum(sorted(ms_each)[len(ms_each) // 2 - 1:len(ms_each) // 2 + 1]), 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"Myrtle-10 NNGP, 32x32x3 correlated-Gaussian images (length scale 3 px), "
-                               f"one {n}x{n} Gram block (x1 != x2), sigma_w2=2, sigma_b2=0",
-                   "n1": n, "n2": n, "depth": list(depth), "pairs": pairs},
-        "model_tflops_whole_step": round(whole, 3),
-        "kernels_ms_per_step": {k: round(v[1] / a.steps, 3) for k, v in prof.items()},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "parity": parity,
-        "fwd_bwd": fwd_bwd,
-        "batched_tiles": batched,
-        "ntk": ntk,
-        "myrtle7_64x64": m64,
-        "fc3_gram": pcg.pop("fc_gram") if pcg else None,
-        "pcg": pcg,
-        "cv8": cv8,
-        "approx_solvers": approx,
-        "context": "paper: ~300 GPU-hours for the full CIFAR-10 Myrtle kernel (hardware and precision not stated)",
-    }
-    print(json.dumps(rec))
+    # Side legs, in order of importance, each with an estimate of its wall
+    # time: a leg that would end past the budget is skipped by name.
+    legs = [
+        ("fwd_bwd", 20.0, a.no_fwd_bwd, lambda: _fwd_bwd(torch)),
+        ("batched_tiles", 75.0, a.no_batched, lambda: _batched(torch, a.batched_full, a.batched_reps)),
+        ("ntk", 12.0, a.no_ntk, lambda: _ntk(torch)),
+        ("cv8", 15.0, a.no_cv8, lambda: _cv8(torch, not a.no_cpu_baseline)),
+        ("myrtle7_64x64", 10.0, a.no_64, lambda: _myrtle64(torch)),
+        ("pcg", 35.0, a.no_pcg, lambda: _pcg(torch, not a.no_cpu_baseline)),
+        ("approx_solvers", 30.0, a.no_approx, lambda: _approx(torch)),
+    ]
+    for name, est, off, fn in legs:
+        if off:
+            rec[name] = None
+            continue
+        if _elapsed() + est > a.budget_s:
+            rec[name] = {"skipped": "budget", "estimated_s": est, "elapsed_s": round(_elapsed(), 1)}
+            print(f"[{_elapsed():.1f} s] {name}: skipped (budget)", file=sys.stderr, flush=True)
+            continue
+        t = time.perf_counter()
+        res = fn()
+        res["leg_wall_s"] = round(time.perf_counter() - t, 2)
+        if name == "pcg":
+            rec["fc3_gram"] = res.pop("fc_gram")
+        rec[name] = res
+        print(f"[{_elapsed():.1f} s] {name}: done in {res['leg_wall_s']} s", file=sys.stderr, flush=True)
+    rec["wall_s"] = round(_elapsed(), 1)
+    _emit(rec)
 
 
 if __name__ == "__main__":
