@@ -44,17 +44,55 @@ def test_ntk_matches_joint_matrix_form(hw, depth, sb2):
             assert abs(kt[a, b] - mt) <= 1e-12 * abs(mt)
 
 
+def _ntk_planted(x1, x2, depth, sw2, sb2, bias_in_T=True, readout_tangent=True):
+    """The joint-matrix NTK with a mistake planted on request: the bias
+    dropped from the pre-activation tangent kernel (T' = box(C) instead of
+    box(C) + sigma_b2), or the readout's own tangent (the NNGP term) left out."""
+    x1 = np.asarray(x1, dtype=np.float64)
+    x2 = np.asarray(x2, dtype=np.float64)
+    h, w, c = x1.shape
+    X = np.concatenate([x1.reshape(h * w, c), x2.reshape(h * w, c)], axis=0)
+    M = X @ X.T / c
+    P = np.zeros_like(M)
+    for s, d in enumerate(depth):
+        T = [matrix_form._blockdiag(matrix_form._shift(h, w, dy, dx)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        for _ in range(d):
+            M = sw2 / 9.0 * sum(t @ M @ t.T for t in T) + sb2
+            Th = (M if bias_in_T else M - sb2) + sw2 / 9.0 * sum(t @ P @ t.T for t in T)
+            q = np.diag(M).copy()
+            P = matrix_form._Fdot(M, q[:, None], q[None, :]) * Th
+            M = matrix_form._F(M, q[:, None], q[None, :])
+        if s + 1 < len(depth):
+            Q = matrix_form._blockdiag(matrix_form._avg2(h, w))
+            M = Q @ M @ Q.T
+            P = Q @ P @ Q.T
+            h, w = h // 2, w // 2
+    n = h * w
+    tangent = float(sw2 * P[:n, n:].mean())
+    return tangent + (float(sw2 * M[:n, n:].mean() + sb2) if readout_tangent else 0.0)
+
+
 @pytest.mark.parametrize("depth,sb2", [((1, 1), 0.0), ((2, 1), 0.5)])
 def test_ntk_matches_finite_width_networks(depth, sb2):
     x = synth.correlated_images(3, 4, 4, 3, 1.5, 77)
     net = oracle.Myrtle(depth, 2.0, sb2)
     _, kt = oracle.myrtle_ntk_gram(x, None, net)
-    width, seeds = 1024, 12
+    width, seeds = 1024, 24
     ests = np.array([mc_nets.myrtle_empirical_ntk(x, depth, 2.0, sb2, width, s) for s in range(seeds)])
     m = ests.mean(0)
     se = ests.std(0, ddof=1) / math.sqrt(seeds)
-    # sampling error plus the O(1/width) finite-width bias
-    assert np.all(np.abs(m - kt) <= 4 * se + 2.0 * np.abs(kt) / width * 10)
+    # sampling error (about 0.9 % of each entry here) plus an O(1/width)
+    # finite-width bias of at most 5 / width (0.5 %)
+    band = 4 * se + 5.0 * np.abs(kt) / width
+    assert np.all(np.abs(m - kt) <= band)
+    # The band is narrow enough to reject plausible mistakes of the recursion,
+    # planted in a copy of the joint-matrix form: without the readout's
+    # tangent the kernel drops by 50-85 %, without the bias in T (sb2 > 0) by
+    # about 20 %.
+    planted = [dict(readout_tangent=False)] + ([dict(bias_in_T=False)] if sb2 > 0 else [])
+    for kw in planted:
+        kv = np.array([[_ntk_planted(x[a], x[b], depth, 2.0, sb2, **kw) for b in range(3)] for a in range(3)])
+        assert np.all(np.abs(m - kv) > band), kw
 
 
 @pytest.mark.parametrize("depth,sb2,sw2", [((2, 1, 1), 0.0, 2.0), ((1, 2), 0.3, 1.5)])
