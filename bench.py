@@ -32,7 +32,8 @@ PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_hbm_counters.md")
 PCG_PMC_FILE = os.path.join(ROOT, "profiles", "pcg_kmv_32768_hbm_counters.md")
 PCG_SRC = os.path.join(ROOT, "paper_2303_05420_amd", "csrc", "pcg.hip")
 # the sources the stage-1 kernel is compiled from (its counters are void once any of them changes)
-STAGE_SRCS = [os.path.join(ROOT, "paper_2303_05420_amd", "csrc", f) for f in ("stage_kernel.h", "nk_tile.h", "nk_common.h")]
+STAGE_SRCS = [os.path.join(ROOT, "paper_2303_05420_amd", "csrc", f)
+              for f in ("stage32.hip", "stage_kernel.h", "nk_tile.h", "nk_common.h")]
 VALU_PMC_FILE = os.path.join(ROOT, "profiles", "myrtle_stage1_n32_valu_counters.md")
 
 

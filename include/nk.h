@@ -148,7 +148,11 @@ int nk_myrtle_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, con
  * infinite-width limit.  The same pass yields the NNGP, written to K_nngp if
  * it is not NULL (both blocks share ldk).  Same shapes, symmetric-block rule,
  * workspace convention (op NK_OP_MYRTLE_NTK) and stream semantics as
- * nk_myrtle_nngp.
+ * nk_myrtle_nngp.  Where a pair's two images are identical (the diagonal of
+ * a symmetric block, or two arrays holding the same image element for
+ * element) its displacement-0 correlation is taken as exactly 1 at every
+ * layer: the derivative of the ReLU map has an infinite slope there, so a
+ * rounded correlation would cost about 1e-4 of relative accuracy.
  */
 int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg, float* K_ntk,
                   float* K_nngp, int64_t ldk, void* ws, size_t ws_bytes, void* stream);
@@ -162,9 +166,13 @@ int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, cons
  * block (x1 == x2, n1 == n2) the full dK is used (entries (a, b) and (b, a)
  * both contribute) and the gradient for the shared images goes to dx1; dx2
  * must then be NULL or equal to dx1.  Covariances are recomputed from the
- * inputs (no state is kept from the forward call).  Gradients use float32
- * atomics for per-image accumulation, so they are reproducible only up to
- * float32 rounding order.
+ * inputs (no state is kept from the forward call).  The per-image sums are
+ * accumulated in float64 with atomic adds (one per workgroup and pixel, in
+ * no fixed order) and rounded to float32 at the end, so gradients are
+ * reproducible up to float64 rounding order.  Where a pair's two images are
+ * identical (the diagonal of a symmetric block, or two arrays holding the
+ * same image element for element) the displacement-0 correlation is taken
+ * as exactly 1, where d/drho of the ReLU map has an infinite slope.
  */
 int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_myrtle_cfg* cfg,
                             const float* dK, int64_t lddk, float* dx1, float* dx2, float* dsigma, void* ws,
@@ -200,6 +208,36 @@ int nk_krr_predict(const float* K_train, int64_t n, const float* K_test, int64_t
 int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t m, const float* Y_s,
                         const float* Y_t, int64_t c, double ridge, int ridge_is_relative, float* dK_ss,
                         float* dK_ts, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of the held-out kernel-ridge-regression error through the Myrtle
+ * NNGP, with respect to learnable support images and both variances (the
+ * differentiable use of the kernel: support images regressed onto target
+ * images):
+ *   K_ss = k(x_s, x_s), K_ts = k(x_t, x_s),  alpha = (K_ss + lambda I)^{-1} Y_s,
+ *   L = mean((K_ts alpha - Y_t)^2),  lambda = ridge (or ridge * mean diag
+ *   K_ss with ridge_is_relative != 0), held fixed (not differentiated).
+ * One call runs the whole step in the library: both Gram blocks
+ * (nk_myrtle_nngp), the float64 solve and its cotangents
+ * (nk_krr_mse_backward), the adjoint of both blocks (nk_myrtle_nngp_backward)
+ * with the support images' contributions of the two blocks summed on the
+ * device before the self-chain reverse, and the casts.
+ *   x_s (n, H, W, C), x_t (m, H, W, C): float32 device images, different
+ *   arrays; Y_s (n x c), Y_t (m x c) float32 device, row-major.
+ *   dx_s (n, H, W, C) float32 device output = dL/dx_s (may be NULL);
+ *   dsigma (2 floats, device) = dL/dsigma_w2, dL/dsigma_b2 (may be NULL);
+ *   *loss (host) = L; *lambda_used (host, may be NULL) = lambda.
+ * 1 <= n <= 16384.  Workspace: nk_krr_mse_grad_workspace(cfg, n, m, c)
+ * bytes (a smaller one, down to one pair per pass, runs in more passes).
+ * Synchronises `stream` (the loss is read on the host between the solve and
+ * the adjoint); NK_ENOTPD if K_ss + lambda I is not positive definite.
+ */
+int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s, const float* Y_t,
+                    int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative, float* dx_s,
+                    float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for nk_krr_mse_grad (0 if the arguments are invalid). */
+size_t nk_krr_mse_grad_workspace(const nk_myrtle_cfg* cfg, int64_t n, int64_t m, int64_t c);
 
 /*
  * Many Myrtle Gram tiles of uneven size in one scheduled pass (the paper

@@ -112,6 +112,11 @@ def lib():
     L.nk_krr_mse_backward.argtypes = [P, i64, P, i64, P, P, i64, ctypes.c_double, ci, P, P,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P, sz, P]
     L.nk_krr_mse_backward.restype = ci
+    L.nk_krr_mse_grad.argtypes = [P, i64, P, i64, P, P, i64, ctypes.POINTER(MyrtleCfg), ctypes.c_double, ci, P, P,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P, sz, P]
+    L.nk_krr_mse_grad.restype = ci
+    L.nk_krr_mse_grad_workspace.argtypes = [ctypes.POINTER(MyrtleCfg), i64, i64, i64]
+    L.nk_krr_mse_grad_workspace.restype = sz
     L.nk_myrtle_nngp_batched.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg), P, sz, P, i32]
     L.nk_myrtle_nngp_batched.restype = ci
     L.nk_myrtle_nngp_batched_workspace.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg)]

@@ -1,11 +1,12 @@
 """Generates the float32 coefficients of the ReLU arc-cosine map used by the
-HIP kernels (nk_common.h, NK_J1_C0..NK_J1_C5).
+HIP kernels (nk_common.h: NK_J1_C0..NK_J1_C4 of the degree-4 fit,
+NK_J1D3_C0..NK_J1D3_C3 of the degree-3 fit, NK_ACOS_C0..NK_ACOS_C6).
 
 For cos t = rho in [0, 1] write u = 1 - rho.  The normalised map
 J1(rho) = (sin t + (pi - t) rho) / pi satisfies J1 = rho + u^{3/2} H(u) with H
 analytic on [0, 1] (H(0) = 2 sqrt(2) / (3 pi)): sin t - t cos t is t^3 times
 an even series and t^2 is u times an analytic series.  H is fitted by a
-polynomial of degree 4 minimising the maximum relative error of J1 (weight
+polynomial of degree 4 (and one of degree 3) minimising the maximum relative error of J1 (weight
 u^{3/2} / J1), using Lawson's iteratively reweighted least squares on 4000
 Chebyshev points, with H evaluated in 40-digit arithmetic.  Negative rho uses
 J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
@@ -21,7 +22,7 @@ import mpmath as mp
 import numpy as np
 
 
-def main(degree: int = 4, m: int = 4000):
+def main(degree: int = 4, m: int = 4000, prefix: str = "NK_J1_C"):
     mp.mp.dps = 40
 
     def j1(rho):
@@ -49,7 +50,7 @@ def main(degree: int = 4, m: int = 4000):
         lw /= lw.sum()
     print(f"max relative error of J1 (float64 evaluation): {e.max():.3e}")
     for k, ck in enumerate(c.astype(np.float32)):
-        print(f"#define NK_J1_C{k} {float(ck)!r}f")
+        print(f"#define {prefix}{k} {float(ck)!r}f")
 
 
 def main_acos(degree: int = 6, m: int = 3000):
@@ -80,4 +81,5 @@ def main_acos(degree: int = 6, m: int = 3000):
 
 if __name__ == "__main__":
     main()
+    main(3, prefix="NK_J1D3_C")
     main_acos()

@@ -381,11 +381,12 @@ int run_batched_stages(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles
       a.D = net.depth[s];
       a.sb2 = net.sb2;
       a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      a.img_floats = (int64_t)net.hw * net.hw * net.C;
       const bool pool = s + 1 < net.S;
       a.in = s > 0 ? bufs[s] : nullptr;
       a.out = pool ? bufs[s + 1] : nullptr;
       if (bp.persist) {
-        const int occ = nk::stage_occupancy(net.hw >> s, net.depth[s], s == 0, pool, net.sb2 != 0.f);
+        const int occ = nk::stage_occupancy(net.hw >> s, net.depth[s], s == 0, pool, net.sb2 != 0.f, net.C);
         const int cus = cu_count();
         if (occ <= 0 || cus <= 0) return hip_fail("occupancy query");
         const int N = net.hw >> s;
@@ -554,6 +555,7 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
       a.D = net.depth[s];
       a.sb2 = net.sb2;
       a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      a.img_floats = (int64_t)net.hw * net.hw * net.C;
       const bool pool = s + 1 < net.S;
       a.in = s > 0 ? bufs[s] : nullptr;
       a.out = pool ? bufs[s + 1] : nullptr;
@@ -570,6 +572,104 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
   return NK_OK;
 }
 
+
+int check_bwd_lds(const NetDesc& net) {
+  for (int s = 0; s < net.S; ++s)
+    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0) > kLdsDynamicMax)
+      return fail(NK_EUNSUPPORTED, "adjoint of stage %d needs more than 160 KiB of LDS", s);
+  return NK_OK;
+}
+
+// Adjoint pair passes of one Gram block for the cotangent dK: adds the
+// table adjoints of both images into W1 / W2, the seed gradients into
+// xb1 / xb2 and the sigma terms into sums (nothing is cleared; the self-chain
+// reverse and the casts are the caller's).  Per chunk: the forward stages up
+// to the last stage's input (the checkpoints), then the adjoint stages in
+// reverse order.
+int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym, const float* dK,
+              int64_t lddk, const float2* tab1, const float2* tab2, double* W1, double* W2, double* xb1, double* xb2,
+              double* sums, float* const* bufs, float* const* gbufs, int64_t chunk, hipStream_t s) {
+  const int tl = nk::table_len(net);
+  const int64_t npairs = nk::pair_count(n1, n2, sym);
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, npairs - p0);
+    for (int st = 0; st + 1 < net.S; ++st) {
+      nk::StageArgs a;
+      memset(&a, 0, sizeof a);
+      a.n1 = n1; a.n2 = n2; a.sym = sym ? 1 : 0; a.T = kPairTile; a.p0 = p0; a.np = np;
+      a.x1 = x1; a.x2 = x2; a.tab1 = tab1; a.tab2 = tab2;
+      a.tablen = tl; a.taboff = nk::table_off(net, st);
+      a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      a.img_floats = (int64_t)net.hw * net.hw * net.C;
+      a.in = st > 0 ? bufs[st] : nullptr;
+      a.out = bufs[st + 1];
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", st + 1, net.hw >> st);
+      ProfScope ps(nm, s);
+      if (nk::launch_stage(net.hw >> st, a, st == 0, true, net.sb2 != 0.f, s)) return hip_fail("stage kernel");
+    }
+    for (int st = net.S - 1; st >= 0; --st) {
+      nk::StageBwdArgs b;
+      memset(&b, 0, sizeof b);
+      b.n1 = n1; b.n2 = n2; b.sym = sym ? 1 : 0; b.T = kPairTile; b.p0 = p0; b.np = np;
+      b.x1 = x1; b.x2 = x2; b.tab1 = tab1; b.tab2 = tab2;
+      b.tablen = tl; b.taboff = nk::table_off(net, st);
+      b.C = net.C; b.D = net.depth[st]; b.sb2 = net.sb2; b.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      b.img_floats = (int64_t)net.hw * net.hw * net.C;
+      b.in = st > 0 ? bufs[st] : nullptr;
+      b.gin = st + 1 < net.S ? gbufs[st + 1] : nullptr;
+      b.gout = st > 0 ? gbufs[st] : nullptr;
+      b.dK = dK; b.lddk = lddk; b.last = st + 1 == net.S ? 1 : 0;
+      b.W1 = W1; b.W2 = W2; b.xbar1 = xb1; b.xbar2 = xb2; b.sums = sums;
+      char nm[48];
+      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d_bwd", st + 1, net.hw >> st);
+      ProfScope ps(nm, s);
+      if (nk::launch_stage_bwd(net.hw >> st, b, st == 0, s)) return hip_fail("adjoint stage kernel");
+    }
+  }
+  return NK_OK;
+}
+
+// Workspace of nk_krr_mse_grad: both Gram blocks and their cotangents, the
+// tables, adjoint sums and gradients of both image sets, the ridge solve and
+// the chunk buffers (each stage's checkpoint and its adjoint).
+struct KrrGradPlan {
+  size_t kss = 0, kts = 0, dss = 0, dts = 0, tab_s = 0, tab_t = 0, scratch = 0, krr = 0, krr_bytes = 0;
+  size_t W_s = 0, W_t = 0, xb_s = 0, xb_t = 0, sums = 0, bscratch = 0;
+  size_t buf[NK_MAX_STAGES] = {0, 0, 0, 0}, gbuf[NK_MAX_STAGES] = {0, 0, 0, 0};
+  size_t total = 0;
+};
+
+KrrGradPlan plan_krr_grad(const NetDesc& net, int64_t n, int64_t m, int64_t c, int64_t chunk) {
+  KrrGradPlan p;
+  Bump b;
+  const size_t tl = (size_t)nk::table_len(net);
+  const size_t img = (size_t)net.hw * net.hw * net.C;
+  p.kss = b.take(sizeof(float) * (size_t)n * n);
+  p.kts = b.take(sizeof(float) * (size_t)m * n);
+  p.dss = b.take(sizeof(float) * (size_t)n * n);
+  p.dts = b.take(sizeof(float) * (size_t)m * n);
+  p.tab_s = b.take(tl * sizeof(float2) * n);
+  p.tab_t = b.take(tl * sizeof(float2) * m);
+  const int64_t pb = std::min<int64_t>(std::max(n, m), kPrepBlocks);
+  p.scratch = b.take((size_t)nk::prep_scratch_doubles(net) * sizeof(double) * pb);
+  p.krr_bytes = krr_plan(n, std::max(m, c)).total;
+  p.krr = b.take(p.krr_bytes);
+  p.W_s = b.take(tl * sizeof(double) * n);
+  p.W_t = b.take(tl * sizeof(double) * m);
+  p.xb_s = b.take(img * sizeof(double) * n);
+  p.xb_t = b.take(img * sizeof(double) * m);
+  p.sums = b.take(4 * sizeof(double));
+  const int64_t pbb = std::min<int64_t>(std::max(n, m), kPrepBwdBlocks);
+  p.bscratch = b.take((size_t)nk::prep_bwd_scratch_doubles(net) * sizeof(double) * pbb);
+  for (int s = 1; s < net.S; ++s) {
+    const size_t q = (size_t)(net.hw >> s);
+    p.buf[s] = b.take(q * q * q * q * sizeof(float) * chunk);
+    p.gbuf[s] = b.take(q * q * q * q * sizeof(float) * chunk);
+  }
+  p.total = b.off + 256;
+  return p;
+}
 
 // ---- CNN-VEC ---------------------------------------------------------------
 
@@ -989,6 +1089,7 @@ int nk_myrtle_ntk(const float* x1, int64_t n1, const float* x2, int64_t n2, cons
       a.x1 = x1; a.x2 = x2; a.tab1 = tab1; a.tab2 = tab2;
       a.tablen = nk::table_len(net); a.taboff = nk::table_off(net, st);
       a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
+      a.img_floats = (int64_t)net.hw * net.hw * net.C;
       const bool pool = st + 1 < net.S;
       a.in = st > 0 ? bufA[st] : nullptr;
       a.in2 = st > 0 ? bufC[st] : nullptr;
@@ -1020,9 +1121,7 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
   if (!ws) return fail(NK_EINVAL, "workspace is NULL");
   const bool sym = (x1 == x2) && (n1 == n2);
   if (sym && dx2 && dx2 != dx1) return fail(NK_EINVAL, "symmetric block: dx2 must be NULL or equal to dx1");
-  for (int s = 0; s < net.S; ++s)
-    if (nk::stage_bwd_lds_bytes(net.hw >> s, net.depth[s], s == 0) > kLdsDynamicMax)
-      return fail(NK_EUNSUPPORTED, "adjoint of stage %d needs more than 160 KiB of LDS", s);
+  if ((rc = check_bwd_lds(net))) return rc;
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   const int64_t chunk = max_chunk_bwd(net, n1, n2, sym, ws_bytes, npairs);
   if (chunk < 1)
@@ -1055,42 +1154,8 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
     bufs[st] = at<float>(ws, p.buf[st]);
     gbufs[st] = at<float>(ws, p.gbuf[st]);
   }
-  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
-    const int64_t np = std::min(chunk, npairs - p0);
-    // forward up to the last stage's input (the checkpoints of the adjoint)
-    for (int st = 0; st + 1 < net.S; ++st) {
-      nk::StageArgs a;
-      memset(&a, 0, sizeof a);
-      a.n1 = n1; a.n2 = n2; a.sym = sym ? 1 : 0; a.T = kPairTile; a.p0 = p0; a.np = np;
-      a.x1 = x1; a.x2 = x2; a.tab1 = tab1; a.tab2 = tab2;
-      a.tablen = tl; a.taboff = nk::table_off(net, st);
-      a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
-      a.in = st > 0 ? bufs[st] : nullptr;
-      a.out = bufs[st + 1];
-      char nm[48];
-      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", st + 1, net.hw >> st);
-      ProfScope ps(nm, s);
-      if (nk::launch_stage(net.hw >> st, a, st == 0, true, net.sb2 != 0.f, s)) return hip_fail("stage kernel");
-    }
-    for (int st = net.S - 1; st >= 0; --st) {
-      nk::StageBwdArgs b;
-      memset(&b, 0, sizeof b);
-      b.n1 = n1; b.n2 = n2; b.sym = sym ? 1 : 0; b.T = kPairTile; b.p0 = p0; b.np = np;
-      b.x1 = x1; b.x2 = x2; b.tab1 = tab1; b.tab2 = tab2;
-      b.tablen = tl; b.taboff = nk::table_off(net, st);
-      b.C = net.C; b.D = net.depth[st]; b.sb2 = net.sb2; b.seed_scale = net.sw2 / 9.0f / (float)net.C;
-      b.in = st > 0 ? bufs[st] : nullptr;
-      b.gin = st + 1 < net.S ? gbufs[st + 1] : nullptr;
-      b.gout = st > 0 ? gbufs[st] : nullptr;
-      b.dK = dK; b.lddk = lddk; b.last = st + 1 == net.S ? 1 : 0;
-      b.W1 = W1; b.W2 = W2; b.xbar1 = xb1; b.xbar2 = xb2; b.sums = sums;
-      char nm[48];
-      snprintf(nm, sizeof nm, "myrtle_stage%d_n%d_bwd", st + 1, net.hw >> st);
-      ProfScope ps(nm, s);
-      if (nk::launch_stage_bwd(net.hw >> st, b, st == 0, s))
-        return hip_fail("adjoint stage kernel");
-    }
-  }
+  if ((rc = bwd_block(net, x1, n1, x2, n2, sym, dK, lddk, tab1, tab2, W1, W2, xb1, xb2, sums, bufs, gbufs, chunk, s)))
+    return rc;
   {
     ProfScope ps("myrtle_self_bwd", s);
     double* bs = at<double>(ws, p.bscratch);
@@ -1170,6 +1235,100 @@ int nk_krr_mse_backward(const float* K_ss, int64_t n, const float* K_ts, int64_t
 }
 
 
+
+size_t nk_krr_mse_grad_workspace(const nk_myrtle_cfg* cfg, int64_t n, int64_t m, int64_t c) {
+  NetDesc net;
+  if (n <= 0 || m <= 0 || c <= 0 || check_myrtle(cfg, &net)) return 0;
+  const int64_t np = std::max(nk::pair_count(n, n, 1), nk::pair_count(m, n, 0));
+  return plan_krr_grad(net, n, m, c, std::min(np, kDefaultChunk)).total;
+}
+
+int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s, const float* Y_t,
+                    int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative, float* dx_s,
+                    float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream) {
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!x_s || !x_t || !Y_s || !Y_t || !loss) return fail(NK_EINVAL, "null pointer argument");
+  if (n <= 0 || m <= 0 || c <= 0) return fail(NK_EINVAL, "need n, m, c > 0");
+  if (x_s == x_t) return fail(NK_EINVAL, "x_s and x_t must be different arrays");
+  if (!(ridge >= 0.0)) return fail(NK_EINVAL, "ridge must be >= 0");
+  if (n > 16384) return fail(NK_EUNSUPPORTED, "n > 16384");
+  if ((rc = check_bwd_lds(net))) return rc;
+  if (!ws) return fail(NK_EINVAL, "workspace is NULL");
+  const int64_t np = std::max(nk::pair_count(n, n, 1), nk::pair_count(m, n, 0));
+  int64_t chunk = std::min(np, kDefaultChunk);
+  KrrGradPlan p = plan_krr_grad(net, n, m, c, chunk);
+  if (ws_bytes < p.total) {
+    // fewer pairs per pass if the workspace is short of the default
+    const size_t fixed = plan_krr_grad(net, n, m, c, 0).total;
+    size_t per = 0;
+    for (int s = 1; s < net.S; ++s) {
+      const size_t q = (size_t)(net.hw >> s);
+      per += 2 * q * q * q * q * sizeof(float);
+    }
+    if (ws_bytes < fixed + 256 * 2 * NK_MAX_STAGES + per)
+      return fail(NK_EINVAL, "workspace too small (need %zu bytes)", nk_krr_mse_grad_workspace(cfg, n, m, c));
+    chunk = std::min<int64_t>(chunk, (int64_t)((ws_bytes - fixed - 256 * 2 * NK_MAX_STAGES) / per));
+    p = plan_krr_grad(net, n, m, c, chunk);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  float* kss = at<float>(ws, p.kss);
+  float* kts = at<float>(ws, p.kts);
+  float* dss = at<float>(ws, p.dss);
+  float* dts = at<float>(ws, p.dts);
+  float2* tab_s = at<float2>(ws, p.tab_s);
+  float2* tab_t = at<float2>(ws, p.tab_t);
+  double* W_s = at<double>(ws, p.W_s);
+  double* W_t = at<double>(ws, p.W_t);
+  double* xb_s = at<double>(ws, p.xb_s);
+  double* xb_t = at<double>(ws, p.xb_t);
+  double* sums = at<double>(ws, p.sums);
+  const int tl = nk::table_len(net);
+  const int64_t img = (int64_t)net.hw * net.hw * net.C;
+  float* bufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  float* gbufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
+  for (int st = 1; st < net.S; ++st) {
+    bufs[st] = at<float>(ws, p.buf[st]);
+    gbufs[st] = at<float>(ws, p.gbuf[st]);
+  }
+  {
+    ProfScope ps("myrtle_prepare", s);
+    if (nk::launch_prepare(x_s, n, net, tab_s, at<double>(ws, p.scratch), kPrepBlocks, s) ||
+        nk::launch_prepare(x_t, m, net, tab_t, at<double>(ws, p.scratch), kPrepBlocks, s))
+      return hip_fail("prepare kernel");
+  }
+  // forward: K_ss (symmetric) and K_ts
+  if ((rc = run_myrtle_pairs(net, x_s, n, x_s, n, true, tab_s, tab_s, kss, n, bufs, chunk, s))) return rc;
+  if ((rc = run_myrtle_pairs(net, x_t, m, x_s, n, false, tab_t, tab_s, kts, n, bufs, chunk, s))) return rc;
+  // ridge solve, loss and the cotangents of both blocks (synchronises)
+  if ((rc = nk_krr_mse_backward(kss, n, kts, m, Y_s, Y_t, c, ridge, ridge_is_relative, dss, dts, loss, lambda_used,
+                                at<char>(ws, p.krr), p.krr_bytes, stream)))
+    return rc;
+  // both adjoints into one set of sums for the support images (x_s is x1 of
+  // the symmetric block and x2 of the cross block)
+  if (nk::launch_zero_f64(W_s, n * tl, s) || nk::launch_zero_f64(xb_s, n * img, s) ||
+      nk::launch_zero_f64(W_t, m * tl, s) || nk::launch_zero_f64(xb_t, m * img, s) || nk::launch_zero_f64(sums, 4, s))
+    return hip_fail("zero");
+  if ((rc = bwd_block(net, x_s, n, x_s, n, true, dss, n, tab_s, tab_s, W_s, W_s, xb_s, xb_s, sums, bufs, gbufs, chunk,
+                      s)))
+    return rc;
+  if ((rc = bwd_block(net, x_t, m, x_s, n, false, dts, n, tab_t, tab_s, W_t, W_s, xb_t, xb_s, sums, bufs, gbufs, chunk,
+                      s)))
+    return rc;
+  {
+    // the self-chain reverse is linear in W: once per image set on the summed
+    // sums.  The targets' chain is run too: their variance maps depend on
+    // both sigmas (their image gradient is not returned).
+    ProfScope ps("myrtle_self_bwd", s);
+    if (nk::launch_prepare_bwd(x_s, n, net, W_s, tl, xb_s, sums, at<double>(ws, p.bscratch), kPrepBwdBlocks, s) ||
+        nk::launch_prepare_bwd(x_t, m, net, W_t, tl, xb_t, sums, at<double>(ws, p.bscratch), kPrepBwdBlocks, s))
+      return hip_fail("self adjoint");
+  }
+  if (dx_s && nk::launch_cast_grad(xb_s, dx_s, n * img, s)) return hip_fail("cast");
+  if (dsigma && nk::launch_finish_sigma(sums, (double)net.sw2, dsigma, s)) return hip_fail("sigma");
+  return ok();
+}
 
 int nk_krr_nystrom(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,
                    const float* K_mn, int64_t m, int64_t ld_mn, const float* Y, int64_t c, double lambda,
@@ -1561,7 +1720,7 @@ int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle
     }
   }
   for (int st = 0; st < net.S; ++st)
-    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f))
+    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f, net.C))
       return hip_fail("stage kernel attributes");
   if (!have) {
     {

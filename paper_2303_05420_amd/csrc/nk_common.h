@@ -16,6 +16,17 @@
 #define NK_J1_C3 -7.56633744458668e-05f
 #define NK_J1_C4 0.0005524527514353395f
 
+// The same form with a degree-3 fit of H (gen_relu_poly.py; max relative
+// error of J1 1.3e-6 in exact arithmetic), one FMA less per entry-layer.
+// Used by the forward NNGP kernels only: over the 9 ReLU layers of Myrtle-10
+// it keeps the normalised kernel error near 2e-6, but the adjoint and the
+// tangent kernel differentiate the map, which amplifies the fit error, so
+// they keep the degree-4 fit.
+#define NK_J1D3_C0 0.3000355064868927f
+#define NK_J1D3_C1 0.015479165129363537f
+#define NK_J1D3_C2 0.0013594607589766383f
+#define NK_J1D3_C3 0.001435322454199195f
+
 // acos(1 - u) = sqrt(u) G(u); G is our own degree-6 fit on [0, 1]
 // (gen_relu_poly.py; dJ1/drho = 1 - acos(rho)/pi to 2.8e-8).
 #define NK_ACOS_C0 1.414214849472046f
@@ -138,6 +149,27 @@ __device__ __forceinline__ float relu_poly(float u) {
   p = __builtin_fmaf(p, u, NK_J1_C1);
   p = __builtin_fmaf(p, u, NK_J1_C0);
   return p;
+}
+
+__device__ __forceinline__ float relu_poly3(float u) {
+  float p = NK_J1D3_C3;
+  p = __builtin_fmaf(p, u, NK_J1D3_C2);
+  p = __builtin_fmaf(p, u, NK_J1D3_C1);
+  p = __builtin_fmaf(p, u, NK_J1D3_C0);
+  return p;
+}
+
+// j1_nonneg and j1_signed_vr (below) with the degree-3 fit (forward NNGP).
+__device__ __forceinline__ float j1_nonneg3(float rho) {
+  float u = __builtin_amdgcn_fmed3f(1.0f - rho, 0.0f, 1.0f);
+  float sq = __builtin_amdgcn_sqrtf(u);
+  return __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly3(u), 1.0f), 1.0f);
+}
+__device__ __forceinline__ float j1_signed_vr3(float v, float rr) {
+  const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-__builtin_fabsf(v), rr, 1.0f), 0.0f, 1.0f);
+  const float c = __builtin_amdgcn_fmed3f(__builtin_fmaf(v, rr, 1.0f), 0.0f, 1.0f);
+  const float sq = __builtin_amdgcn_sqrtf(u);
+  return __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly3(u), 1.0f), c);
 }
 
 // J1 for rho >= 0 (every ReLU after the first: inputs are sums of

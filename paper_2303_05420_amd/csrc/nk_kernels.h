@@ -64,6 +64,7 @@ struct StageArgs {
   int tablen, taboff;
   int C, D;
   float sb2, seed_scale;
+  int64_t img_floats;  // floats per input image (H W C): the tangent kernel compares the two images of a pair
   const float* in;  // [np][N][N][N][N]      (stages after the first)
   float* out;       // [np][N/2][N/2][N/2][N/2] (pooling stages)
   float* K;         // final stage (NULL: not written)
@@ -87,6 +88,7 @@ struct StageBwdArgs {
   int tablen, taboff;
   int C, D;
   float sb2, seed_scale;
+  int64_t img_floats;  // floats per input image (H W C), for the identical-image test of a pair
   const float* in;    // stage input [np][N]^4 (stages after the first)
   const float* gin;   // adjoint of the next stage's input [np][N/2]^4 (all but the last stage)
   float* gout;        // adjoint of this stage's input [np][N]^4 (stages after the first)
@@ -134,9 +136,13 @@ size_t stage64_lds_bytes(int D, int C);
 int launch_stage64(const StageArgs& a, bool bias, hipStream_t s);
 size_t stage_ntk_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage_ntk(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
-int prime_stage(int N, int D, bool seed, bool pool, bool bias);  // kernel attributes, no launch
+int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C);  // kernel attributes, no launch
 int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t stream);
-int stage_occupancy(int N, int D, bool seed, bool pool, bool bias);  // resident workgroups per CU
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C);  // resident workgroups per CU
+// the 32x32 pooling stage with two tile columns per lane (stage32.hip)
+size_t stage32_lds_bytes(int D, bool seed);
+int launch_stage32(const StageArgs& a, bool seed, bool bias, hipStream_t s);
+int stage32_occupancy(int D, bool seed, bool bias, int C);
 int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream);
 size_t stage_bwd_lds_bytes(int N, int D, bool seed);
 int launch_stage_bwd(int N, const StageBwdArgs& a, bool seed, hipStream_t s);

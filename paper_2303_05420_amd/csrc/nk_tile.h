@@ -51,12 +51,31 @@ __device__ __forceinline__ float hsum3(float x, float mL, float mR) {
   return h;
 }
 
+// Settles the candidates (same == 2) of the PPWG slots: a pair of two
+// arrays holding the same image element for element counts as identical
+// (same = 1), because then its displacement-0 correlation is 1 exactly at
+// every layer, as on the diagonal of a symmetric block.  Every thread of the
+// workgroup calls this (the loop condition is uniform).
+template <int PPWG, int THREADS>
+__device__ inline void identical_pairs(int* same, const float* const* x1, const float* const* x2,
+                                       int64_t nfl) {
+  for (int s = 0; s < PPWG; ++s) {
+    if (same[s] != 2) continue;
+    int eq = 1;
+    for (int64_t e = threadIdx.x; e < nfl; e += THREADS) eq &= (x1[s][e] == x2[s][e]) ? 1 : 0;
+    eq = __syncthreads_and(eq);
+    if (threadIdx.x == 0) same[s] = eq ? 1 : 0;
+  }
+  __syncthreads();
+}
+
 // wave-uniform 0/1 factor (kept in a scalar register)
 __device__ __forceinline__ float uniform_mask(bool zero) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, zero ? 0.f : 1.f)));
 }
 
-// One [3x3 conv, ReLU] layer on a tile held as A[r] (row r, this lane's column).
+// One [3x3 conv, ReLU] layer on a tile held as A[r] (row r, this lane's
+// column), forward NNGP (the map with the degree-3 fit).
 template <int N, bool SIGNED, bool BIAS>
 __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restrict__ c1,
                                            const float2* __restrict__ c2, int seam, float mL, float mR,
@@ -74,7 +93,7 @@ __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restri
     const float2 a = c1[r * N];
     const float2 b = c2[r * N];
     const float rr = a.x * b.x;
-    const float J = SIGNED ? j1_signed_vr(v, rr) : j1_nonneg(v * rr);
+    const float J = SIGNED ? j1_signed_vr3(v, rr) : j1_nonneg3(v * rr);
     A[r] = (a.y * b.y) * J;
     hm = h0;
     h0 = hp;

@@ -6,7 +6,8 @@ namespace nk {
 
 // Resident workgroups per CU of a stage kernel (and sets its LDS attribute,
 // so that a later launch makes no attribute call, e.g. under graph capture).
-int stage_occupancy(int N, int D, bool seed, bool pool, bool bias) {
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C) {
+  if (N == 32 && pool) return stage32_occupancy(D, seed, bias, C);
   switch (N) {
     case 2: return occ_n<2, false>(D, seed, pool, bias);
     case 4: return occ_n<4, false>(D, seed, pool, bias);
@@ -17,8 +18,8 @@ int stage_occupancy(int N, int D, bool seed, bool pool, bool bias) {
   return -2;
 }
 
-int prime_stage(int N, int D, bool seed, bool pool, bool bias) {
-  const int r = stage_occupancy(N, D, seed, pool, bias);
+int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C) {
+  const int r = stage_occupancy(N, D, seed, pool, bias, C);
   return r < 0 ? r : 0;
 }
 
@@ -47,6 +48,7 @@ int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t str
 }
 
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed) {
+  if (N == 32 && pool) return stage32_lds_bytes(D, seed);
   switch (N) {
     case 2: return KCfg<2>::PPWG * slot_lds_bytes<2>(D, pool, seed);
     case 4: return KCfg<4>::PPWG * slot_lds_bytes<4>(D, pool, seed);
@@ -58,6 +60,8 @@ size_t stage_lds_bytes(int N, int D, bool pool, bool seed) {
 }
 
 int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s) {
+  // 32x32 pooling stages: two tile columns per lane (stage32.hip)
+  if (N == 32 && pool) return launch_stage32(a, seed, bias, s);
   switch (N) {
     case 2: return launch_n<2, false>(a, seed, pool, bias, s);
     case 4: return launch_n<4, false>(a, seed, pool, bias, s);

@@ -123,17 +123,23 @@ __device__ __forceinline__ void bwd_layer_fwd(float (&A)[RPL], const float2* __r
 
 // Reverse of one layer: A holds the layer input, G the adjoint of the layer
 // output on entry and v_bar on return; w is added to the i- and j-sums.
+// J1'(rho) = 1 - acos(rho) / pi has an infinite slope at rho = 1, so a
+// float32 rho rounded by 1e-7 would move it by about 1e-4 where rho is 1
+// exactly: on the displacement-0 tile of a pair of identical images the
+// caller passes umax = 0, which pins u = 1 - rho to 0 there (umax = 1
+// elsewhere: the plain clamp).
 template <int N, int RS, int RPL, bool SGN>
 __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[RPL], const float2* __restrict__ c1,
                                               const float2* __restrict__ c2, int cut, int part, float mL, float mR,
-                                              float sb2, float (&Wi)[RPL], float (&Wj)[RPL], float& sw, float& sb) {
+                                              float sb2, float umax, float (&Wi)[RPL], float (&Wj)[RPL], float& sw,
+                                              float& sb) {
   box_rows<N, RS, RPL>(A, cut, part, mL, mR, [&](int rr, float v) {
     const float2 a = c1[rr * N];
     const float2 b = c2[rr * N];
     const float rr_ = a.x * b.x, ss = a.y * b.y;
     const float rho = (v + sb2) * rr_;
     const float arho = SGN ? __builtin_fabsf(rho) : rho;
-    const float u = __builtin_amdgcn_fmed3f(1.0f - arho, 0.0f, 1.0f);
+    const float u = __builtin_amdgcn_fmed3f(1.0f - arho, 0.0f, umax);
     const float sq = __builtin_amdgcn_sqrtf(u);
     const float J = __builtin_fmaf(u * sq, relu_poly(u), SGN ? __builtin_fmaxf(rho, 0.0f) : rho);
     const float th = sq * acos_g_pi(u);  // acos(|rho|) / pi
@@ -207,6 +213,9 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ int64_t s_pa[PPWG], s_pb[PPWG];
   __shared__ double s_sum[PPWG][2];
+  __shared__ int s_same[PPWG];
+  __shared__ const float* s_x1[PPWG];
+  __shared__ const float* s_x2[PPWG];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -226,8 +235,12 @@ void stage_bwd_kernel(const StageBwdArgs args) {
     s_pb[tid] = b;
     s_sum[tid][0] = 0.0;
     s_sum[tid][1] = 0.0;
+    s_x1[tid] = args.x1 + a * args.img_floats;
+    s_x2[tid] = args.x2 + b * args.img_floats;
+    s_same[tid] = (args.sym && a == b) ? 1 : (s_x1[tid][0] == s_x2[tid][0] ? 2 : 0);
   }
   __syncthreads();
+  identical_pairs<PPWG, THREADS>(s_same, s_x1, s_x2, args.img_floats);
   char* sbase = smem + slot * SLOT;
   float2* t1 = reinterpret_cast<float2*>(sbase);
   float2* t2 = t1 + TL;
@@ -306,6 +319,8 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 #pragma unroll 1
     for (int ky = 0; ky < N; ++ky) {
       const int cut = (ky == 0 ? -N : N - ky) - row0;
+      // displacement-0 tile of a pair of identical images: rho = 1 exactly
+      const float umax = (s_same[slot] == 1 && ky == 0 && kx == 0) ? 0.f : 1.f;
       float A[RPL], G[RPL];
       // Every read of the LDS images and tables below goes through an
       // opaque offset, so that repeated reads of one address in the layer
@@ -361,9 +376,9 @@ void stage_bwd_kernel(const StageBwdArgs args) {
         const float2* c1 = t1 + z + l * NN + row0 * N + ix;
         const float2* c2 = t2 + z + l * 2 * NN + (ky + row0) * N + jx;
         if (SEED && l == 0)
-          bwd_layer_rev<N, RS, RPL, true>(A, G, c1, c2, cut, part, mL, mR, sb2, Wi[l], Wj[l], sw, sb);
+          bwd_layer_rev<N, RS, RPL, true>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
         else
-          bwd_layer_rev<N, RS, RPL, false>(A, G, c1, c2, cut, part, mL, mR, sb2, Wi[l], Wj[l], sw, sb);
+          bwd_layer_rev<N, RS, RPL, false>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
         bwd_box<N, RS, RPL>(G, cut, part, mL, mR);
       }
       // G = adjoint of the stage input

@@ -51,12 +51,14 @@ namespace nk {
 // Pair p of the pass -> table rows of both images, their pixels (first
 // stage), the element offsets of its kernel value (and of its mirror in a
 // symmetric block, -1 if none) in its output, and whether both images are
-// the same image (the diagonal of a symmetric block).  One block: the block order of
-// pair_of.  Batched pass: the tile holding p (binary search over the tiles'
-// first pairs), then its block order.
+// the same image (the diagonal of a symmetric block; with `detect`, 2 marks
+// a pair of distinct images whose first elements agree, a candidate for
+// identical_pairs below).  One block: the block order of pair_of.  Batched
+// pass: the tile holding p (binary search over the tiles' first pairs), then
+// its block order.
 __device__ inline void resolve_pair(const StageArgs& a, int64_t p, int64_t img_floats, int64_t* t1, int64_t* t2,
                                     const float** x1, const float** x2, float** kbase, int64_t* off,
-                                    int64_t* offm, int* same) {
+                                    int64_t* offm, int* same, bool detect) {
   int64_t ia, ib;
   if (a.tiles == nullptr) {
     pair_of(p, a.n1, a.n2, a.sym, a.T, &ia, &ib);
@@ -68,6 +70,7 @@ __device__ inline void resolve_pair(const StageArgs& a, int64_t p, int64_t img_f
     *kbase = a.K;
     *off = ia * a.ldk + ib;
     *offm = (a.sym && ia != ib) ? ib * a.ldk + ia : -1;
+    if (detect && !*same && (*x1)[0] == (*x2)[0]) *same = 2;
     return;
   }
   int lo = 0, hi = a.ntiles - 1;
@@ -88,7 +91,9 @@ __device__ inline void resolve_pair(const StageArgs& a, int64_t p, int64_t img_f
   *kbase = t.K;
   *off = ia * t.ldk + ib;
   *offm = (t.sym && ia != ib) ? ib * t.ldk + ia : -1;
+  if (detect && !*same && (*x1)[0] == (*x2)[0]) *same = 2;
 }
+
 
 // Work units (groups of PPWG consecutive pairs of the chunk) of this
 // workgroup.  Plain grid: one unit per workgroup, XCD-remapped.  Persistent
@@ -141,10 +146,11 @@ __global__ __launch_bounds__((KCfg<N, NTK>::THREADS)) void stage_kernel(const St
   if (tid < PPWG) {
     int64_t pl = unit * PPWG + tid;
     if (pl >= args.np) pl = args.np - 1;
-    resolve_pair(args, args.p0 + pl, (int64_t)N * N * args.C, &s_t1[tid], &s_t2[tid], &s_x1[tid], &s_x2[tid],
-                 &s_k[tid], &s_off[tid], &s_offm[tid], &s_same[tid]);
+    resolve_pair(args, args.p0 + pl, args.img_floats, &s_t1[tid], &s_t2[tid], &s_x1[tid], &s_x2[tid],
+                 &s_k[tid], &s_off[tid], &s_offm[tid], &s_same[tid], NTK);
   }
   __syncthreads();
+  if constexpr (NTK) identical_pairs<PPWG, THREADS>(s_same, s_x1, s_x2, args.img_floats);
   // this stage's (alpha, beta) tables of both images -> LDS; x2's rows twice
   for (int e = tid; e < PPWG * TL; e += THREADS) {
     const int s = e / TL, r = e - s * TL;

@@ -149,13 +149,18 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
                          sigma_w2: float = 2.0, sigma_b2: float = 0.0, need_dx: bool = True,
                          ws: torch.Tensor | None = None):
     """Adjoint of myrtle_nngp: returns (dx1, dx2, dsigma[2]) for cotangent dK.
-    For x2=None (symmetric block) dx2 is None and dx1 holds the whole gradient."""
+    For x2=None (symmetric block) dx2 is None and dx1 holds the whole gradient.
+    An x2 that shares x1's memory (same start, same count) asks for the two
+    partial gradients separately, so it is passed as a copy: the library reads
+    an aliased pair of arguments as one symmetric block."""
     _check_images(x1, "x1")
     sym = x2 is None
     if sym:
         x2 = x1
     else:
         _check_images(x2, "x2")
+        if x2.data_ptr() == x1.data_ptr() and x2.shape[0] == x1.shape[0]:
+            x2 = x2.clone()
     n1, h, w, c = x1.shape
     n2 = x2.shape[0]
     if dK.shape != (n1, n2) or dK.dtype != torch.float32 or not dK.is_cuda:
@@ -177,6 +182,43 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
         ws.data_ptr(), ws.numel(), _stream(x1.device))
     _lib.check(rc)
     return dx1, dx2, ds
+
+
+def krr_mse_grad(x_s: torch.Tensor, y_s: torch.Tensor, x_t: torch.Tensor, y_t: torch.Tensor, depth: Sequence[int],
+                 sigma_w2: float = 2.0, sigma_b2: float = 0.0, ridge: float = 1e-4, relative: bool = True,
+                 ws: torch.Tensor | None = None):
+    """nk_krr_mse_grad: (loss, dL/dx_s, dL/d[sigma_w2, sigma_b2], lambda) of the
+    held-out squared error of kernel ridge regression of the support images
+    x_s (labels y_s) onto the targets x_t (labels y_t); lambda = ridge (times
+    mean diag K_ss when relative) is held fixed."""
+    _check_images(x_s, "x_s")
+    _check_images(x_t, "x_t")
+    for t, nm in ((y_s, "y_s"), (y_t, "y_t")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2:
+            raise TypeError(f"{nm} must be a contiguous float32 CUDA matrix")
+    n, h, w, c = x_s.shape
+    m = x_t.shape[0]
+    k = y_s.shape[1]
+    if x_t.shape[1:] != x_s.shape[1:] or y_s.shape[0] != n or y_t.shape != (m, k):
+        raise ValueError("shape mismatch")
+    if x_t.data_ptr() == x_s.data_ptr():
+        x_t = x_t.clone()
+    cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
+    if ws is None:
+        need = int(_lib.lib().nk_krr_mse_grad_workspace(ctypes.byref(cfg), n, m, k))
+        if need == 0:
+            raise ValueError("invalid network or sizes for nk_krr_mse_grad")
+        ws = workspace(need, x_s.device)
+    dx = torch.empty_like(x_s)
+    ds = torch.empty(2, dtype=torch.float32, device=x_s.device)
+    loss = ctypes.c_double(0.0)
+    lam = ctypes.c_double(0.0)
+    rc = _lib.lib().nk_krr_mse_grad(x_s.data_ptr(), n, x_t.data_ptr(), m, y_s.data_ptr(), y_t.data_ptr(), k,
+                                    ctypes.byref(cfg), float(ridge), 1 if relative else 0, dx.data_ptr(),
+                                    ds.data_ptr(), ctypes.byref(loss), ctypes.byref(lam), ws.data_ptr(), ws.numel(),
+                                    _stream(x_s.device))
+    _lib.check(rc)
+    return loss.value, dx, ds, lam.value
 
 
 def cv_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 8, sigma_w2: float = 2.0,

@@ -144,3 +144,45 @@ def test_batched_uneven_myrtle7_32x32_sample(nk):
         got = tiles[t][2].cpu().numpy()[r, c]
         err = float(np.max(np.abs(got - v) / np.sqrt(d1 * d2)))
         assert err <= TOL, f"tile {t}: {err:.2e}"
+
+
+@pytest.mark.timeout(600)
+def test_batched_full_uneven_tile_list_sampled(nk):
+    """The uneven-tile workload at its stated size: 64 Myrtle-7 tiles with
+    sides U{32..2048} over prefixes of two pools of 2048 32x32x3 images, one
+    batched pass (hipGraph); 4 seeded oracle entries per tile, and the two
+    smallest tiles bitwise equal to the one-block entry point."""
+    w = synth.WORKLOADS["myrtle7_uneven64"]
+    depth = w["depth"]
+    shapes = [tuple(int(v) for v in s) for s in synth.uneven_tile_shapes(w["n_tiles"], w["lo"], w["hi"],
+                                                                         w["seeds"][2])]
+    pa = synth.correlated_images(w["pool"], 32, 32, 3, w["length"], w["seeds"][0])
+    pb = synth.correlated_images(w["pool"], 32, 32, 3, w["length"], w["seeds"][1])
+    xa, xb = _gpu(pa), _gpu(pb)
+    tiles = _tiles_from_shapes(xa, xb, shapes)
+    _say(f"batched full workload: {len(tiles)} tiles, {sum(a * b for a, b in shapes)} pairs")
+    nk.myrtle_nngp_batched(tiles, depth, graph=True)
+    torch.cuda.synchronize()
+    _say("  batched pass done")
+    small = sorted(range(len(shapes)), key=lambda t: shapes[t][0] * shapes[t][1])[:2]
+    for t in small:
+        x1, x2, out = tiles[t]
+        assert np.array_equal(out.cpu().numpy(), nk.myrtle_nngp(x1, x2, depth).cpu().numpy()), f"tile {t}"
+    rng = np.random.default_rng(w["seeds"][2] + 2)
+    rows = [rng.integers(0, a, 4) for a, _ in shapes]
+    cols = [rng.integers(0, b, 4) for _, b in shapes]
+    ia = np.unique(np.concatenate(rows))
+    ib = np.unique(np.concatenate(cols))
+    net = oracle.Myrtle(depth)
+    _say(f"  oracle: {len(ia) + len(ib)} self recursions, {4 * len(shapes)} entries")
+    qa, da = oracle.myrtle_self(pa[ia], net)
+    qb, db = oracle.myrtle_self(pb[ib], net)
+    pos_a = {int(v): i for i, v in enumerate(ia)}
+    pos_b = {int(v): i for i, v in enumerate(ib)}
+    loc = np.array([[pos_a[int(r)], pos_b[int(c)]] for rr, cc in zip(rows, cols) for r, c in zip(rr, cc)])
+    ref = oracle.myrtle_pairs(pa[ia], pb[ib], loc, net, qa, qb)
+    got = np.concatenate([tiles[t][2][torch.as_tensor(rows[t]).cuda(), torch.as_tensor(cols[t]).cuda()].cpu().numpy()
+                          for t in range(len(shapes))])
+    err = float(np.max(np.abs(got - ref) / np.sqrt(da[loc[:, 0]] * db[loc[:, 1]])))
+    _say(f"  normalised error over {len(ref)} entries: {err:.3e}")
+    assert err <= TOL

@@ -76,10 +76,12 @@ def test_ntk_nngp_agrees_with_nngp_entry_point(nk):
     x2 = synth.correlated_images(11, 16, 16, 3, 2.0, 65)
     th, k = nk.myrtle_ntk(_gpu(x1), _gpu(x2), (2, 1, 1), with_nngp=True)
     k0 = nk.myrtle_nngp(_gpu(x1), _gpu(x2), (2, 1, 1))
-    # same recursion, pooled sums in another order: float32 rounding only
+    # same recursion; the NNGP entry point evaluates the ReLU map with the
+    # degree-3 fit (relative error of the map 1.3e-6), the tangent kernel
+    # with the degree-4 fit (1.3e-7), and sums in another order
     err = float((k - k0).abs().max() / k0.abs().max())
     _say(f"  NNGP of the NTK pass vs the NNGP entry point: {err:.2e}")
-    assert err <= 1e-6
+    assert err <= 5e-6
 
 
 def test_ntk_myrtle10_32x32_sampled(nk):
