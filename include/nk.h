@@ -130,6 +130,22 @@ int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const n
                int64_t ldk, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * nk_fc_nngp for callers that cannot allocate (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): no workspace argument
+ * and no allocation of any kind.  Its only scratch, the first-layer
+ * diagonals of both sets (n1 + n2 floats), lives in a static device array of
+ * 2^21 floats (8 MiB) that each device holds until the process ends; the
+ * device address of the current device's copy is looked up on its first
+ * call.  n1 + n2 > 2^21 returns NK_EINVAL.  Same arguments, layout, stream
+ * semantics and results (bitwise) as nk_fc_nngp.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device
+ * (different streams, or host threads) race on it and must be serialised by
+ * the caller.
+ */
+int nk_fc_nngp_static(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_fc_cfg* cfg, float* K,
+                      int64_t ldk, void* stream);
+
+/*
  * Myrtle NNGP block: K[a, b] = k_Myrtle(x1[a], x2[b]) with x* (n*, H, W, C).
  * Accuracy: float32 arithmetic; |K - K_exact| / sqrt(K(x,x) K(x',x')) is of
  * order 1e-6 for the networks above.  Deterministic: the same inputs give

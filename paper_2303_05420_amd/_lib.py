@@ -101,6 +101,8 @@ def lib():
     L.nk_workspace_size.restype = sz
     L.nk_fc_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(FcCfg), P, i64, P, sz, P]
     L.nk_fc_nngp.restype = ci
+    L.nk_fc_nngp_static.argtypes = [P, i64, P, i64, ctypes.POINTER(FcCfg), P, i64, P]
+    L.nk_fc_nngp_static.restype = ci
     L.nk_myrtle_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, i64, P, sz, P]
     L.nk_myrtle_nngp.restype = ci
     L.nk_myrtle_ntk.argtypes = [P, i64, P, i64, ctypes.POINTER(MyrtleCfg), P, P, i64, P, sz, P]

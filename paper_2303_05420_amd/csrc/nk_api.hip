@@ -16,6 +16,13 @@
 
 using nk::NetDesc;
 
+// Scratch of nk_fc_nngp_static: the first-layer diagonals of both image
+// sets (n1 + n2 floats).  One copy per device, held until the process ends.
+// Host code never names it as an address: the device address of each
+// device's copy comes from hipGetSymbolAddress (see fc_static_scratch).
+constexpr int64_t kFcStaticFloats = (int64_t)1 << 21;  // 8 MiB: n1 + n2 <= 2,097,152
+static __device__ __align__(256) float scratch[kFcStaticFloats];
+
 namespace {
 
 thread_local std::string g_err;
@@ -136,6 +143,30 @@ int check_myrtle(const nk_myrtle_cfg* c, NetDesc* net, bool allow64 = false) {
     if (lds > kLdsDynamicMax)
       return fail(NK_EUNSUPPORTED, "stage %d needs more than 160 KiB of LDS", s);
   }
+  return NK_OK;
+}
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+int fc_static_scratch(float** out) {
+  static std::atomic<float*> addr[nk::kMaxDevices];
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail("hipGetDevice");
+  if (dev < 0 || dev >= nk::kMaxDevices) return fail(NK_EUNSUPPORTED, "device index %d out of range", dev);
+  float* p = addr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> g(mu);
+    p = addr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      void* q = nullptr;
+      if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q)
+        return hip_fail("hipGetSymbolAddress(scratch)");
+      p = static_cast<float*>(q);
+      addr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
   return NK_OK;
 }
 
@@ -998,6 +1029,35 @@ int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const n
   a.ldk = ldk;
   ProfScope ps("fc_nngp", (hipStream_t)stream);
   if (nk::launch_fc(a, d1, d2, (hipStream_t)stream)) return hip_fail("fc kernel");
+  return ok();
+}
+
+int nk_fc_nngp_static(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_fc_cfg* cfg, float* K,
+                      int64_t ldk, void* stream) {
+  if (!cfg || !x1 || !x2 || !K) return fail(NK_EINVAL, "null pointer argument");
+  if (n1 <= 0 || n2 <= 0 || cfg->d <= 0 || cfg->depth < 0) return fail(NK_EINVAL, "sizes must be positive");
+  if (ldk < n2) return fail(NK_EINVAL, "ldk < n2");
+  if (!(cfg->sigma_w2 > 0.f) || !(cfg->sigma_b2 >= 0.f)) return fail(NK_EINVAL, "need sigma_w2 > 0, sigma_b2 >= 0");
+  if (n1 + n2 > kFcStaticFloats)
+    return fail(NK_EINVAL, "n1 + n2 = %lld exceeds the static scratch (%lld rows)", (long long)(n1 + n2),
+                (long long)kFcStaticFloats);
+  float* d = nullptr;
+  int rc = fc_static_scratch(&d);
+  if (rc) return rc;
+  nk::FcArgs a;
+  a.x1 = x1;
+  a.x2 = x2;
+  a.n1 = n1;
+  a.n2 = n2;
+  a.d = cfg->d;
+  a.depth = cfg->depth;
+  a.sw2 = cfg->sigma_w2;
+  a.sb2 = cfg->sigma_b2;
+  a.d1 = d;
+  a.d2 = d + n1;
+  a.K = K;
+  a.ldk = ldk;
+  if (nk::launch_fc(a, d, d + n1, (hipStream_t)stream)) return hip_fail("fc kernel");
   return ok();
 }
 

@@ -127,6 +127,26 @@ def fc_nngp(x1: torch.Tensor, x2: torch.Tensor | None, depth: int = 3, sigma_w2:
     return out
 
 
+def fc_nngp_static(x1: torch.Tensor, x2: torch.Tensor | None, out: torch.Tensor, depth: int = 3,
+                   sigma_w2: float = 2.0, sigma_b2: float = 0.01) -> torch.Tensor:
+    """nk_fc_nngp_static: the FC NNGP block into the caller's `out` with no
+    allocation at all (the library's static scratch holds the diagonals)."""
+    if x2 is None:
+        x2 = x1
+    a = x1.reshape(x1.shape[0], -1)
+    b = x2.reshape(x2.shape[0], -1)
+    for t, nm in ((a, "x1"), (b, "x2")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous float32 CUDA tensor")
+    if a.shape[1] != b.shape[1] or out.shape[0] < a.shape[0] or out.shape[1] < b.shape[0]:
+        raise ValueError("shape mismatch")
+    cfg = _lib.FcCfg(int(a.shape[1]), int(depth), float(sigma_w2), float(sigma_b2))
+    rc = _lib.lib().nk_fc_nngp_static(a.data_ptr(), a.shape[0], b.data_ptr(), b.shape[0], ctypes.byref(cfg),
+                                      out.data_ptr(), out.stride(0), _stream(a.device))
+    _lib.check(rc)
+    return out
+
+
 def krr_predict(k_train: torch.Tensor, k_test: torch.Tensor, y: torch.Tensor, ridge_rel: float) -> torch.Tensor:
     """pred = K_test (K_train + lambda I)^{-1} Y with lambda = ridge_rel mean diag (float64 inside)."""
     for t, nm in ((k_train, "k_train"), (k_test, "k_test"), (y, "y")):
