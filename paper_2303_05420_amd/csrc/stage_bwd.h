@@ -108,14 +108,39 @@ __device__ __forceinline__ void box_rows(const float (&X)[RPL], int cut, int par
   }
 }
 
+// The tables of this lane's rows, each requested two rows before its use:
+// at one wave per SIMD nothing else hides the LDS latency.  (The compiler
+// barrier keeps each request ahead of the row it runs before.)
+template <int N, int RPL>
+struct RowTables {
+  float2 a[RPL], b[RPL];
+  const float2* c1;
+  const float2* c2;
+  __device__ __forceinline__ RowTables(const float2* p1, const float2* p2) : c1(p1), c2(p2) {
+    fetch(0);
+    if (RPL > 1) fetch(1);
+  }
+  __device__ __forceinline__ void fetch(int rr) {
+    a[rr] = c1[rr * N];
+    b[rr] = c2[rr * N];
+  }
+  // before row rr is computed
+  __device__ __forceinline__ void advance(int rr) {
+    if (rr + 2 < RPL) fetch(rr + 2);
+    asm volatile("" ::: "memory");
+  }
+};
+
 // Forward [3x3 conv, ReLU] layer on this lane's rows (recompute).
 template <int N, int RS, int RPL, bool SGN>
 __device__ __forceinline__ void bwd_layer_fwd(float (&A)[RPL], const float2* __restrict__ c1,
                                               const float2* __restrict__ c2, int cut, int part, float mL, float mR,
                                               float sb2) {
+  RowTables<N, RPL> t(c1, c2);
   box_rows<N, RS, RPL>(A, cut, part, mL, mR, [&](int rr, float v) {
-    const float2 a = c1[rr * N];
-    const float2 b = c2[rr * N];
+    t.advance(rr);
+    const float2 a = t.a[rr];
+    const float2 b = t.b[rr];
     const float rho = (v + sb2) * (a.x * b.x);
     A[rr] = (a.y * b.y) * (SGN ? j1_signed(rho) : j1_nonneg(rho));
   });
@@ -133,9 +158,11 @@ __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[
                                               const float2* __restrict__ c2, int cut, int part, float mL, float mR,
                                               float sb2, float umax, float (&Wi)[RPL], float (&Wj)[RPL], float& sw,
                                               float& sb) {
+  RowTables<N, RPL> t(c1, c2);
   box_rows<N, RS, RPL>(A, cut, part, mL, mR, [&](int rr, float v) {
-    const float2 a = c1[rr * N];
-    const float2 b = c2[rr * N];
+    t.advance(rr);
+    const float2 a = t.a[rr];
+    const float2 b = t.b[rr];
     const float rr_ = a.x * b.x, ss = a.y * b.y;
     const float rho = (v + sb2) * rr_;
     const float arho = SGN ? __builtin_fabsf(rho) : rho;
