@@ -58,6 +58,17 @@ __host__ __device__ constexpr size_t bwd_slot_lds_bytes(int D, bool seed) {
   return (((size_t)D * N * N * 24 + (seed ? (size_t)N * N * 48 : 0)) + 16 + 15) & ~(size_t)15;
 }
 
+// Exchange between the two 32-lane halves of a wave (one VALU instruction,
+// v_permlane32_swap, instead of a round trip through the LDS crossbar).  The
+// instruction swaps the upper 32 lanes of its first operand with the lower
+// 32 lanes of its second, so lane l < 32 gets x(l + 32) and lane l >= 32
+// gets y(l - 32).
+__device__ __forceinline__ float halves_swap(float x, float y, int part) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                                  false, false);
+  return __builtin_bit_cast(float, part ? r[0] : r[1]);
+}
+
 // h-values of the rows just outside this lane's rows (the row above the first
 // and the one below the last), from the other half of the column.
 template <int N, int RS>
@@ -66,7 +77,9 @@ __device__ __forceinline__ void edge_rows(float hfirst, float hlast, int part, f
     hup = 0.f;
     hdn = 0.f;
   } else {
-    const float recv = __shfl_xor(part ? hfirst : hlast, N);
+    static_assert(N == 32, "the two row halves of a column are the two halves of a wave");
+    // upper half: the lower half's last row; lower half: the upper half's first row
+    const float recv = halves_swap(hfirst, hlast, part);
     hup = part ? recv : 0.f;
     hdn = part ? 0.f : recv;
   }
@@ -194,8 +207,8 @@ __device__ __forceinline__ void bwd_box(float (&G)[RPL], int cut, int part, floa
 // j-frame accumulators one row up (after a ky step): row rr takes row rr + 1,
 // the last row takes the first row of the next lane group (cyclically).
 template <int N, int RS, int RPL>
-__device__ __forceinline__ void rot_rows(float (&A)[RPL]) {
-  const float first = RS == 1 ? A[0] : __shfl_xor(A[0], N);
+__device__ __forceinline__ void rot_rows(float (&A)[RPL], int part) {
+  const float first = RS == 1 ? A[0] : halves_swap(A[0], A[0], part);
 #pragma unroll
   for (int rr = 0; rr + 1 < RPL; ++rr) A[rr] = A[rr + 1];
   A[RPL - 1] = first;
@@ -436,9 +449,9 @@ void stage_bwd_kernel(const StageBwdArgs args) {
       sbd += sb;
       // j-frame follows the sweep to ky + 1
 #pragma unroll
-      for (int l = 0; l < D; ++l) rot_rows<N, RS, RPL>(Wj[l]);
+      for (int l = 0; l < D; ++l) rot_rows<N, RS, RPL>(Wj[l], part);
 #pragma unroll
-      for (int c = 0; c < CC; ++c) rot_rows<N, RS, RPL>(Xj[c]);
+      for (int c = 0; c < CC; ++c) rot_rows<N, RS, RPL>(Xj[c], part);
     }
   }
   // j-sums back to lane ix <-> pixel column ix (the frame is at the last column)
