@@ -42,25 +42,37 @@ __host__ __device__ constexpr int s64_x1_rows(int C) { return C <= 3 ? 16 : 0; }
 
 // [3x3 conv, ReLU] on one 64-row tile; as tile_layer, with the second
 // image's table rows wrapping: row r of tile (ky, kx) reads pixel row
-// (r + ky) mod 64 of x2.
+// (r + ky) mod 64 of x2.  The map is the forward NNGP's degree-3 fit, and
+// each row's tables are requested two rows before its map (at two waves per
+// SIMD the LDS latency is not hidden by other waves alone; the compiler
+// barrier keeps each request ahead of the row it runs before).
 template <bool SIGNED, bool BIAS>
 __device__ __forceinline__ void s64_layer(float (&A)[64], const float2* __restrict__ c1,
                                           const float2* __restrict__ t2l, int ky, int jx, int seam, float mL,
                                           float mR, float sb2) {
+  float2 ta[64], tb[64];  // (registers: three rows live at a time)
+  auto fetch = [&](int r) {
+    ta[r] = c1[r * 64];
+    tb[r] = t2l[((r + ky) & 63) * 64 + jx];
+  };
+  fetch(0);
+  fetch(1);
   float hm = 0.f;
   float h0 = hsum3(A[0], mL, mR);
 #pragma unroll
   for (int r = 0; r < 64; ++r) {
+    if (r + 2 < 64) fetch(r + 2);
+    asm volatile("" ::: "memory");
     float hp = 0.f;
     if (r + 1 < 64) hp = hsum3(A[r + 1], mL, mR);
     float v = h0;
     if (r > 0) v = __builtin_fmaf(uniform_mask(r == seam), hm, v);
     if (r + 1 < 64) v = __builtin_fmaf(uniform_mask(r + 1 == seam), hp, v);
     if (BIAS) v += sb2;
-    const float2 a = c1[r * 64];
-    const float2 b = t2l[((r + ky) & 63) * 64 + jx];
+    const float2 a = ta[r];
+    const float2 b = tb[r];
     const float rr = a.x * b.x;
-    const float J = SIGNED ? j1_signed_vr(v, rr) : j1_nonneg(v * rr);
+    const float J = SIGNED ? j1_signed_vr3(v, rr) : j1_nonneg3(v * rr);
     A[r] = (a.y * b.y) * J;
     hm = h0;
     h0 = hp;
