@@ -293,7 +293,9 @@ def _batched(torch, full: bool, reps: int = 3):
             "speedup_median": round(mp / mb, 4),
             "ranges_disjoint": bool(max(times["batched"]) < min(times["plain"])
                                     or max(times["plain"]) < min(times["batched"])),
-            "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands)}
+            "bitwise_equal": bool(same), "schedule": chosen, "candidates_tried": len(cands),
+            "shape_candidates_us_per_pair": {f"x{c['wg_pairs_mult']}": round(c["us_per_pair"], 4)
+                                             for c in cands if c["kind"] == "shape"}}
 
 
 def _cv8(torch, cpu: bool):

@@ -273,9 +273,12 @@ size_t nk_krr_mse_grad_workspace(const nk_myrtle_cfg* cfg, int64_t n, int64_t m,
  * the workspace allows), side of the image tile that orders pairs (8, 16,
  * 32), and a persistent grid (all workgroups resident, the workgroups of
  * each XCD walking one contiguous range of the work list) or one workgroup
- * per work unit -- and keeps the fastest for the process
- * (nk_myrtle_batched_tuning reports the timings).  That call synchronises
- * `stream`; later calls do not.
+ * per work unit -- and keeps the fastest; under that schedule it then
+ * times the stage kernels of tiles of at most 16 x 16 (the later stages of
+ * a 32 x 32 network) with one and with two pairs-per-workgroup multiples and
+ * keeps the faster kernel shape, for the process (nk_myrtle_batched_tuning
+ * reports the timings).  Results do not depend on the choices.  That call
+ * synchronises `stream`; later calls do not.
  *
  * If `graph` is non-zero the pass (table preparation and all stage
  * launches) is captured into a hipGraph the first time this exact pass is
@@ -291,20 +294,36 @@ int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle
  * arguments are invalid). */
 size_t nk_myrtle_nngp_batched_workspace(const nk_tile* tiles, int32_t ntiles, const nk_myrtle_cfg* cfg);
 
-/* One timed schedule candidate of the batched pass. */
+/* One timed candidate of the batched pass: a schedule (kind 0, first stage
+ * timed) or, under the chosen schedule, a kernel shape of the stages of tiles
+ * of at most 16 x 16 (kind 1, those stages timed together). */
 typedef struct {
-  int64_t chunk;      /* pairs per stage pass */
-  int32_t pair_tile;  /* image-tile side of the pair order */
-  int32_t persistent; /* 1: persistent XCD-ordered grid, 0: one workgroup per unit */
-  double us_per_pair; /* measured first-stage time per pair */
+  int64_t chunk;         /* pairs per stage pass */
+  int32_t pair_tile;     /* image-tile side of the pair order */
+  int32_t persistent;    /* 1: persistent XCD-ordered grid, 0: one workgroup per unit */
+  double us_per_pair;    /* measured time per pair of the stages timed */
+  int32_t kind;          /* 0: schedule candidate, 1: kernel-shape candidate */
+  int32_t wg_pairs_mult; /* pairs per workgroup of the stage kernels of tiles of at most 16 x 16, as a
+                            multiple (1 or 2) of their smallest workgroup (256 threads); in `chosen`: the
+                            tuned multiple */
 } nk_batched_candidate;
 
 /* Timings of the candidates tried for this network (up to max_entries into
- * out, may be NULL) and the chosen one (into *chosen, may be NULL).  Returns
+ * out, may be NULL) and the chosen schedule and shape (into *chosen, may be
+ * NULL; its us_per_pair is the chosen schedule's first-stage time).  Returns
  * the number of candidates, or NK_EINVAL if no batched pass has been tuned
  * for this configuration in this process. */
 int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
                              nk_batched_candidate* chosen);
+
+/* Fixes the schedule and kernel shape of the batched pass for this network
+ * configuration for the rest of the process, in place of tuning (no timing
+ * is done; nk_myrtle_batched_tuning then reports no candidates and this
+ * choice).  Read from *choice: chunk in [1, 32768] (cut to what the
+ * workspace holds at each call), pair_tile in [1, 256], persistent 0 or 1,
+ * wg_pairs_mult 1 or 2; the other fields are ignored.  Results do not depend
+ * on the choice.  NK_EINVAL on other values or a NULL pointer; no GPU call. */
+int nk_myrtle_batched_set_schedule(const nk_myrtle_cfg* cfg, const nk_batched_candidate* choice);
 
 /*
  * CNN-VEC network (App. "Neural Kernel Architecture", CNN-VEC listing; CV8 =

@@ -49,7 +49,7 @@ class Tile(ctypes.Structure):
 
 class BatchedCandidate(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int64), ("pair_tile", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("us_per_pair", ctypes.c_double)]
+                ("us_per_pair", ctypes.c_double), ("kind", ctypes.c_int32), ("wg_pairs_mult", ctypes.c_int32)]
 
 
 class CvCfg(ctypes.Structure):
@@ -126,6 +126,8 @@ def lib():
     L.nk_myrtle_batched_tuning.argtypes = [ctypes.POINTER(MyrtleCfg), ctypes.POINTER(BatchedCandidate), ci,
                                            ctypes.POINTER(BatchedCandidate)]
     L.nk_myrtle_batched_tuning.restype = ci
+    L.nk_myrtle_batched_set_schedule.argtypes = [ctypes.POINTER(MyrtleCfg), ctypes.POINTER(BatchedCandidate)]
+    L.nk_myrtle_batched_set_schedule.restype = ci
     dbl = ctypes.c_double
     L.nk_cv_nngp.argtypes = [P, i64, P, i64, ctypes.POINTER(CvCfg), P, i64, P, sz, P]
     L.nk_cv_nngp.restype = ci

@@ -279,12 +279,15 @@ T* at(void* ws, size_t off) {
 
 // ---- batched tiles (many uneven Gram tiles in one scheduled pass) --------
 
-// Schedule parameters of a batched pass: pairs per stage pass, image-tile
-// side of the pair order, persistent grid or one workgroup per unit.
+// Schedule and shape of a batched pass: pairs per stage pass, image-tile
+// side of the pair order, persistent grid or one workgroup per unit, and the
+// pairs-per-workgroup multiplier of the stage kernels of tiles of at most
+// 16 x 16.
 struct BatchParams {
   int64_t chunk = kDefaultChunk;
   int T = kPairTile;
   int persist = 0;
+  int ppm = 1;
 };
 
 struct TuneRecord {
@@ -417,11 +420,11 @@ int run_batched_stages(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles
       a.in = s > 0 ? bufs[s] : nullptr;
       a.out = pool ? bufs[s + 1] : nullptr;
       if (bp.persist) {
-        const int occ = nk::stage_occupancy(net.hw >> s, net.depth[s], s == 0, pool, net.sb2 != 0.f, net.C);
+        const int occ =
+            nk::stage_occupancy(net.hw >> s, net.depth[s], s == 0, pool, net.sb2 != 0.f, net.C, bp.ppm);
         const int cus = cu_count();
         if (occ <= 0 || cus <= 0) return hip_fail("occupancy query");
-        const int N = net.hw >> s;
-        const int64_t ppwg = N * N >= 256 ? 1 : 256 / (N * N);  // pairs per workgroup of the stage kernel
+        const int64_t ppwg = nk::stage_pairs_per_wg(net.hw >> s, pool, bp.ppm);
         const int64_t units = (np + ppwg - 1) / ppwg;
         // all workgroups resident (occupancy x CUs), a multiple of the 8 XCDs,
         // and no more than the units to share
@@ -431,15 +434,19 @@ int run_batched_stages(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles
       char nm[48];
       snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", s + 1, net.hw >> s);
       ProfScope ps(nm, stream);
-      if (nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream)) return hip_fail("stage kernel");
+      if (nk::launch_stage(net.hw >> s, a, s == 0, pool, net.sb2 != 0.f, stream, bp.ppm))
+        return hip_fail("stage kernel");
     }
   }
   return NK_OK;
 }
 
 // Times the first-stage kernel of the pass under each schedule candidate on
-// the pass's own first pairs and keeps the fastest (results are identical
-// under every candidate: the schedule only permutes pairs).
+// the pass's own first pairs and keeps the fastest; then, under that
+// schedule, times the stages of tiles of at most 16 x 16 with one and with
+// two pairs-per-workgroup multiples and keeps the faster shape.  Results are
+// identical under every candidate: the schedule only permutes pairs, and a
+// pair's arithmetic does not depend on how many pairs share a workgroup.
 int autotune(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles, const float2* tab, float* const* bufs,
              int64_t npairs, int64_t max_chunk_ws, hipStream_t s, TuneRecord* rec) {
   // pairs per stage pass: the candidates that fit the workspace, cut to the
@@ -477,14 +484,62 @@ int autotune(const NetDesc& net, const nk::TileDesc* ddesc, int ntiles, const fl
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
         nk_batched_candidate cd;
+        memset(&cd, 0, sizeof cd);
         cd.chunk = c;
         cd.pair_tile = T;
         cd.persistent = persist;
         cd.us_per_pair = 1e3 * ms / (double)np;
+        cd.kind = 0;
+        cd.wg_pairs_mult = 1;
         rec->cands.push_back(cd);
         if (cd.us_per_pair < best) {
           best = cd.us_per_pair;
           rec->best = bp;
+        }
+      }
+    }
+  }
+  {
+    // kernel shape of the stages of tiles of at most 16 x 16
+    int first_small = -1;
+    for (int st = 0; st < net.S; ++st)
+      if ((net.hw >> st) <= 16) {
+        first_small = st;
+        break;
+      }
+    if (first_small >= 0) {
+      BatchParams bp = rec->best;
+      const int64_t np = bp.chunk;
+      // inputs of the first such stage for the first np pairs
+      for (int st = 0; st < first_small; ++st)
+        if ((rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, np, st, s))) goto done;
+      double best_shape = 1e30;
+      for (int m = 1; m <= 2; ++m) {
+        bp.ppm = m;
+        for (int rep = 0; rep < 2; ++rep) {  // warm-up, then timed
+          if (rep) hipEventRecord(e0, s);
+          for (int st = first_small; st < net.S; ++st)
+            if ((rc = run_batched_stages(net, ddesc, ntiles, tab, bufs, bp, 0, np, st, s))) goto done;
+        }
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = hip_fail("tuning event");
+          goto done;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        nk_batched_candidate cd;
+        memset(&cd, 0, sizeof cd);
+        cd.chunk = bp.chunk;
+        cd.pair_tile = bp.T;
+        cd.persistent = bp.persist;
+        cd.us_per_pair = 1e3 * ms / (double)np;
+        cd.kind = 1;
+        cd.wg_pairs_mult = m;
+        rec->cands.push_back(cd);
+        if (cd.us_per_pair < best_shape) {
+          best_shape = cd.us_per_pair;
+          rec->best.ppm = m;
         }
       }
     }
@@ -1780,7 +1835,7 @@ int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle
     }
   }
   for (int st = 0; st < net.S; ++st)
-    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f, net.C))
+    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f, net.C, bp.ppm))
       return hip_fail("stage kernel attributes");
   if (!have) {
     {
@@ -1794,6 +1849,10 @@ int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle
     bp = rec.best;
   }
   bp.chunk = std::min(bp.chunk, max_chunk_ws);
+  // (the tuned shape's kernel attributes, before any capture)
+  for (int st = 0; st < net.S; ++st)
+    if (nk::prime_stage(net.hw >> st, net.depth[st], st == 0, st + 1 < net.S, net.sb2 != 0.f, net.C, bp.ppm))
+      return hip_fail("stage kernel attributes");
 
   if (!graph) {
     {
@@ -1807,8 +1866,8 @@ int nk_myrtle_nngp_batched(const nk_tile* tiles, int32_t ntiles, const nk_myrtle
   // graph: captured on a library stream the first time this exact pass is
   // seen (tiles, network, workspace, schedule), replayed afterwards
   char sigb[256];
-  snprintf(sigb, sizeof sigb, "%s|ws%p:%zu|c%lld T%d p%d|", key.c_str(), ws, ws_bytes, (long long)bp.chunk, bp.T,
-           bp.persist);
+  snprintf(sigb, sizeof sigb, "%s|ws%p:%zu|c%lld T%d p%d m%d|", key.c_str(), ws, ws_bytes, (long long)bp.chunk, bp.T,
+           bp.persist, bp.ppm);
   std::string sig(sigb);
   sig.append(reinterpret_cast<const char*>(L.desc.data()), sizeof(nk::TileDesc) * L.desc.size());
   for (auto& im : L.images) sig.append(reinterpret_cast<const char*>(&im), sizeof im);
@@ -1861,6 +1920,27 @@ size_t nk_myrtle_nngp_batched_workspace(const nk_tile* tiles, int32_t ntiles, co
          256 * NK_MAX_STAGES;
 }
 
+int nk_myrtle_batched_set_schedule(const nk_myrtle_cfg* cfg, const nk_batched_candidate* choice) {
+  NetDesc net;
+  int rc = check_myrtle(cfg, &net);
+  if (rc) return rc;
+  if (!choice) return fail(NK_EINVAL, "choice is NULL");
+  if (choice->chunk <= 0 || choice->chunk > 32768) return fail(NK_EINVAL, "chunk must be in [1, 32768]");
+  if (choice->pair_tile < 1 || choice->pair_tile > 256) return fail(NK_EINVAL, "pair_tile must be in [1, 256]");
+  if (choice->persistent != 0 && choice->persistent != 1) return fail(NK_EINVAL, "persistent must be 0 or 1");
+  if (choice->wg_pairs_mult != 1 && choice->wg_pairs_mult != 2) return fail(NK_EINVAL, "wg_pairs_mult must be 1 or 2");
+  BatchParams bp;
+  bp.chunk = choice->chunk;
+  bp.T = choice->pair_tile;
+  bp.persist = choice->persistent;
+  bp.ppm = choice->wg_pairs_mult;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  TuneRecord& r = g_tune[net_key(net)];
+  r.best = bp;
+  r.cands.clear();
+  return ok();
+}
+
 int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out, int max_entries,
                              nk_batched_candidate* chosen) {
   NetDesc net;
@@ -1880,8 +1960,10 @@ int nk_myrtle_batched_tuning(const nk_myrtle_cfg* cfg, nk_batched_candidate* out
     chosen->chunk = r.best.chunk;
     chosen->pair_tile = r.best.T;
     chosen->persistent = r.best.persist;
+    chosen->kind = 0;
+    chosen->wg_pairs_mult = r.best.ppm;
     for (auto& c : r.cands)
-      if (c.chunk == r.best.chunk && c.pair_tile == r.best.T && c.persistent == r.best.persist)
+      if (c.kind == 0 && c.chunk == r.best.chunk && c.pair_tile == r.best.T && c.persistent == r.best.persist)
         chosen->us_per_pair = c.us_per_pair;
   }
   ok();

@@ -130,15 +130,19 @@ int64_t prep_scratch_doubles(const NetDesc& net);
 int launch_prepare(const float* x, int64_t n, const NetDesc& net, float2* tab, double* scratch,
                    int64_t max_blocks, hipStream_t stream);
 size_t stage_lds_bytes(int N, int D, bool pool, bool seed);
-int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
+// ppm: pairs-per-workgroup multiplier (1 or 2) of the stage kernels of tiles
+// of at most 16 x 16 (a kernel-shape choice of the batched pass; results do
+// not depend on it); ignored for larger tiles.
+int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s, int ppm = 1);
 // first stage at 64x64 (seed, D <= 2 layers, pool; plain blocks only)
 size_t stage64_lds_bytes(int D, int C);
 int launch_stage64(const StageArgs& a, bool bias, hipStream_t s);
 size_t stage_ntk_lds_bytes(int N, int D, bool pool, bool seed);
 int launch_stage_ntk(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s);
-int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C);  // kernel attributes, no launch
+int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C, int ppm = 1);  // kernel attributes, no launch
 int launch_put_tiles(const TileDesc* host, int n, TileDesc* dst, hipStream_t stream);
-int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C);  // resident workgroups per CU
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C, int ppm = 1);  // resident workgroups per CU
+int stage_pairs_per_wg(int N, bool pool, int ppm);  // pairs per workgroup of the stage kernel
 // the 32x32 pooling stage with two tile columns per lane (stage32.hip)
 size_t stage32_lds_bytes(int D, bool seed);
 int launch_stage32(const StageArgs& a, bool seed, bool bias, hipStream_t s);

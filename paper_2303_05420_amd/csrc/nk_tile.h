@@ -9,12 +9,15 @@ namespace nk {
 // Workgroup shape of the forward stage kernel.  A segment of N lanes owns
 // CPS tile columns; the 32x32 tangent kernel (two tiles per column plus
 // their pooling rows) takes two columns per segment on half the lanes, so
-// that each wave has twice the registers.
-template <int N, bool NTK = false>
+// that each wave has twice the registers.  PPM multiplies the pairs of one
+// workgroup (tiles of at most 16 x 16: 256 or 512 threads); the arithmetic
+// of a pair does not depend on it.
+template <int N, bool NTK = false, int PPM = 1>
 struct KCfg {
+  static_assert(PPM == 1 || (PPM == 2 && N <= 16), "pairs multiplier 2 only for tiles of at most 16 x 16");
   static constexpr int CPS = (NTK && N == 32) ? 2 : 1;  // tile columns per segment
   static constexpr int LPP = N * N / CPS;                // lanes per pair
-  static constexpr int THREADS = LPP > 256 ? LPP : 256;
+  static constexpr int THREADS = (LPP > 256 ? LPP : 256) * PPM;
   static constexpr int PPWG = THREADS / LPP;
 };
 

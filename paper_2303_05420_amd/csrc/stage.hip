@@ -6,8 +6,18 @@ namespace nk {
 
 // Resident workgroups per CU of a stage kernel (and sets its LDS attribute,
 // so that a later launch makes no attribute call, e.g. under graph capture).
-int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C) {
+// ppm: pairs-per-workgroup multiplier of tiles of at most 16 x 16 (1 or 2;
+// ignored above).
+int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C, int ppm) {
   if (N == 32 && pool) return stage32_occupancy(D, seed, bias, C);
+  if (ppm == 2) {
+    switch (N) {
+      case 2: return occ_n<2, false, 2>(D, seed, pool, bias);
+      case 4: return occ_n<4, false, 2>(D, seed, pool, bias);
+      case 8: return occ_n<8, false, 2>(D, seed, pool, bias);
+      case 16: return occ_n<16, false, 2>(D, seed, pool, bias);
+    }
+  }
   switch (N) {
     case 2: return occ_n<2, false>(D, seed, pool, bias);
     case 4: return occ_n<4, false>(D, seed, pool, bias);
@@ -18,9 +28,15 @@ int stage_occupancy(int N, int D, bool seed, bool pool, bool bias, int C) {
   return -2;
 }
 
-int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C) {
-  const int r = stage_occupancy(N, D, seed, pool, bias, C);
+int prime_stage(int N, int D, bool seed, bool pool, bool bias, int C, int ppm) {
+  const int r = stage_occupancy(N, D, seed, pool, bias, C, ppm);
   return r < 0 ? r : 0;
+}
+
+int stage_pairs_per_wg(int N, bool pool, int ppm) {
+  if (N == 32 && pool) return 1;
+  const int lpp = N * N;
+  return (lpp >= 256 ? 1 : 256 / lpp) * (N <= 16 && ppm == 2 ? 2 : 1);
 }
 
 // Tile table of a batched pass -> device memory through kernel arguments
@@ -59,9 +75,17 @@ size_t stage_lds_bytes(int N, int D, bool pool, bool seed) {
   return 0;
 }
 
-int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s) {
+int launch_stage(int N, const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s, int ppm) {
   // 32x32 pooling stages: two tile columns per lane (stage32.hip)
   if (N == 32 && pool) return launch_stage32(a, seed, bias, s);
+  if (ppm == 2) {
+    switch (N) {
+      case 2: return launch_n<2, false, 2>(a, seed, pool, bias, s);
+      case 4: return launch_n<4, false, 2>(a, seed, pool, bias, s);
+      case 8: return launch_n<8, false, 2>(a, seed, pool, bias, s);
+      case 16: return launch_n<16, false, 2>(a, seed, pool, bias, s);
+    }
+  }
   switch (N) {
     case 2: return launch_n<2, false>(a, seed, pool, bias, s);
     case 4: return launch_n<4, false>(a, seed, pool, bias, s);

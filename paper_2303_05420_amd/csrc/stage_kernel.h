@@ -116,9 +116,9 @@ __device__ inline void unit_range(int64_t nunits, int persist, int64_t* first, i
   *end = (x + 1) * R < nunits ? (x + 1) * R : nunits;
 }
 
-template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
-__global__ __launch_bounds__((KCfg<N, NTK>::THREADS)) void stage_kernel(const StageArgs args) {
-  using Cfg = KCfg<N, NTK>;
+template <int N, bool SEED, bool POOL, bool BIAS, bool NTK, int PPM = 1>
+__global__ __launch_bounds__((KCfg<N, NTK, PPM>::THREADS)) void stage_kernel(const StageArgs args) {
+  using Cfg = KCfg<N, NTK, PPM>;
   constexpr int THREADS = Cfg::THREADS, PPWG = Cfg::PPWG, CPS = Cfg::CPS, LPP = Cfg::LPP;
   constexpr int H = N / 2;
   constexpr int HC = NTK ? H : 1, NC = NTK ? N : 1;  // sizes of the tangent-kernel arrays
@@ -433,52 +433,56 @@ __global__ __launch_bounds__((KCfg<N, NTK>::THREADS)) void stage_kernel(const St
 }
 
 // Allows one instantiation its dynamic LDS on the current device.
-template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
+template <int N, bool SEED, bool POOL, bool BIAS, bool NTK, int PPM>
 int set_attr(size_t lds) {
   static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
-  return allow_dyn_lds((const void*)stage_kernel<N, SEED, POOL, BIAS, NTK>, lds, seen);
+  return allow_dyn_lds((const void*)stage_kernel<N, SEED, POOL, BIAS, NTK, PPM>, lds, seen);
 }
 
-template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
+template <int N, bool SEED, bool POOL, bool BIAS, bool NTK, int PPM>
 int launch_t(const StageArgs& a, hipStream_t stream) {
-  const int64_t nwg = (a.np + KCfg<N, NTK>::PPWG - 1) / KCfg<N, NTK>::PPWG;
-  const size_t lds = (size_t)KCfg<N, NTK>::PPWG * slot_lds_bytes<N>(a.D, POOL, SEED, NTK);
-  if (set_attr<N, SEED, POOL, BIAS, NTK>(lds)) return -3;
+  using Cfg = KCfg<N, NTK, PPM>;
+  const int64_t nwg = (a.np + Cfg::PPWG - 1) / Cfg::PPWG;
+  const size_t lds = (size_t)Cfg::PPWG * slot_lds_bytes<N>(a.D, POOL, SEED, NTK);
+  if (set_attr<N, SEED, POOL, BIAS, NTK, PPM>(lds)) return -3;
   const int64_t grid = a.persist > 0 ? a.persist : nwg;
-  hipLaunchKernelGGL((stage_kernel<N, SEED, POOL, BIAS, NTK>), dim3((unsigned)grid), dim3(KCfg<N, NTK>::THREADS),
-                     lds, stream, a);
+  hipLaunchKernelGGL((stage_kernel<N, SEED, POOL, BIAS, NTK, PPM>), dim3((unsigned)grid), dim3(Cfg::THREADS), lds,
+                     stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-template <int N, bool SEED, bool POOL, bool BIAS, bool NTK>
+template <int N, bool SEED, bool POOL, bool BIAS, bool NTK, int PPM>
 int occ_t(int D) {
-  const size_t lds = (size_t)KCfg<N, NTK>::PPWG * slot_lds_bytes<N>(D, POOL, SEED, NTK);
-  if (set_attr<N, SEED, POOL, BIAS, NTK>(lds)) return -3;
+  using Cfg = KCfg<N, NTK, PPM>;
+  const size_t lds = (size_t)Cfg::PPWG * slot_lds_bytes<N>(D, POOL, SEED, NTK);
+  if (set_attr<N, SEED, POOL, BIAS, NTK, PPM>(lds)) return -3;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<N, SEED, POOL, BIAS, NTK>,
-                                                   KCfg<N, NTK>::THREADS, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, stage_kernel<N, SEED, POOL, BIAS, NTK, PPM>, Cfg::THREADS,
+                                                   lds) != hipSuccess)
     return -3;
   return nb;
 }
 
-template <int N, bool NTK>
+template <int N, bool NTK, int PPM = 1>
 int launch_n(const StageArgs& a, bool seed, bool pool, bool bias, hipStream_t s) {
   if (seed) {
-    if (pool) return bias ? launch_t<N, true, true, true, NTK>(a, s) : launch_t<N, true, true, false, NTK>(a, s);
-    return bias ? launch_t<N, true, false, true, NTK>(a, s) : launch_t<N, true, false, false, NTK>(a, s);
+    if (pool)
+      return bias ? launch_t<N, true, true, true, NTK, PPM>(a, s) : launch_t<N, true, true, false, NTK, PPM>(a, s);
+    return bias ? launch_t<N, true, false, true, NTK, PPM>(a, s) : launch_t<N, true, false, false, NTK, PPM>(a, s);
   }
-  if (pool) return bias ? launch_t<N, false, true, true, NTK>(a, s) : launch_t<N, false, true, false, NTK>(a, s);
-  return bias ? launch_t<N, false, false, true, NTK>(a, s) : launch_t<N, false, false, false, NTK>(a, s);
+  if (pool)
+    return bias ? launch_t<N, false, true, true, NTK, PPM>(a, s) : launch_t<N, false, true, false, NTK, PPM>(a, s);
+  return bias ? launch_t<N, false, false, true, NTK, PPM>(a, s) : launch_t<N, false, false, false, NTK, PPM>(a, s);
 }
 
-template <int N, bool NTK>
+template <int N, bool NTK, int PPM = 1>
 int occ_n(int D, bool seed, bool pool, bool bias) {
   if (seed) {
-    if (pool) return bias ? occ_t<N, true, true, true, NTK>(D) : occ_t<N, true, true, false, NTK>(D);
-    return bias ? occ_t<N, true, false, true, NTK>(D) : occ_t<N, true, false, false, NTK>(D);
+    if (pool) return bias ? occ_t<N, true, true, true, NTK, PPM>(D) : occ_t<N, true, true, false, NTK, PPM>(D);
+    return bias ? occ_t<N, true, false, true, NTK, PPM>(D) : occ_t<N, true, false, false, NTK, PPM>(D);
   }
-  if (pool) return bias ? occ_t<N, false, true, true, NTK>(D) : occ_t<N, false, true, false, NTK>(D);
-  return bias ? occ_t<N, false, false, true, NTK>(D) : occ_t<N, false, false, false, NTK>(D);
+  if (pool) return bias ? occ_t<N, false, true, true, NTK, PPM>(D) : occ_t<N, false, true, false, NTK, PPM>(D);
+  return bias ? occ_t<N, false, false, true, NTK, PPM>(D) : occ_t<N, false, false, false, NTK, PPM>(D);
 }
 
 }  // namespace nk

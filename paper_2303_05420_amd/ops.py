@@ -504,5 +504,16 @@ def batched_tuning(hw: int, c: int, depth: Sequence[int], sigma_w2: float = 2.0,
 
     def d(x):
         return {"chunk": int(x.chunk), "pair_tile": int(x.pair_tile), "persistent": int(x.persistent),
-                "us_per_pair": float(x.us_per_pair)}
+                "us_per_pair": float(x.us_per_pair), "kind": "shape" if x.kind else "schedule",
+                "wg_pairs_mult": int(x.wg_pairs_mult)}
     return [d(buf[i]) for i in range(min(n, 64))], d(ch)
+
+
+def batched_set_schedule(hw: int, c: int, depth: Sequence[int], sigma_w2: float = 2.0, sigma_b2: float = 0.0, *,
+                         chunk: int, pair_tile: int, persistent: int, wg_pairs_mult: int):
+    """Fixes the batched pass's schedule and kernel shape for this network for
+    the rest of the process, in place of tuning (nk_myrtle_batched_set_schedule)."""
+    cfg = _lib.myrtle_cfg(hw, c, depth, sigma_w2, sigma_b2)
+    ch = _lib.BatchedCandidate()
+    ch.chunk, ch.pair_tile, ch.persistent, ch.wg_pairs_mult = chunk, pair_tile, persistent, wg_pairs_mult
+    _lib.check(_lib.lib().nk_myrtle_batched_set_schedule(ctypes.byref(cfg), ctypes.byref(ch)))

@@ -153,6 +153,26 @@ def test_batched_validation():
     assert L.nk_myrtle_batched_tuning(ctypes.byref(cfg), out, 4, None) == _lib.NK_EINVAL
 
 
+def test_batched_set_schedule_validation():
+    # a configuration no other test tunes
+    L = _lib.lib()
+    cfg = _lib.myrtle_cfg(8, 2, (1, 3, 1), 1.7, 0.05)
+    ch = _lib.BatchedCandidate()
+    ch.chunk, ch.pair_tile, ch.persistent, ch.wg_pairs_mult = 4096, 16, 1, 2
+    assert L.nk_myrtle_batched_set_schedule(ctypes.byref(cfg), None) == _lib.NK_EINVAL
+    for field, bad in (("chunk", 0), ("chunk", 32769), ("pair_tile", 0), ("pair_tile", 257), ("persistent", 2),
+                       ("wg_pairs_mult", 3), ("wg_pairs_mult", 0)):
+        b = _lib.BatchedCandidate()
+        ctypes.memmove(ctypes.byref(b), ctypes.byref(ch), ctypes.sizeof(ch))
+        setattr(b, field, bad)
+        assert L.nk_myrtle_batched_set_schedule(ctypes.byref(cfg), ctypes.byref(b)) == _lib.NK_EINVAL, field
+    assert L.nk_myrtle_batched_set_schedule(ctypes.byref(cfg), ctypes.byref(ch)) == _lib.NK_OK
+    out = (_lib.BatchedCandidate * 4)()
+    chosen = _lib.BatchedCandidate()
+    assert L.nk_myrtle_batched_tuning(ctypes.byref(cfg), out, 4, ctypes.byref(chosen)) == 0
+    assert (chosen.chunk, chosen.pair_tile, chosen.persistent, chosen.wg_pairs_mult) == (4096, 16, 1, 2)
+
+
 def test_solver_workspace_and_validation():
     L = _lib.lib()
     p = ctypes.c_void_p(256)

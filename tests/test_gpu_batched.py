@@ -92,9 +92,41 @@ def test_batched_small_uneven_tiles_match_plain_and_oracle(nk):
         assert err <= TOL, f"tile {t}: {err:.2e}"
     cands, chosen = nk.batched_tuning(8, 3, depth)
     _say(f"  tuned: {chosen} of {len(cands)} candidates")
-    assert len(cands) >= 2
+    sched = [c for c in cands if c["kind"] == "schedule"]
+    shape = [c for c in cands if c["kind"] == "shape"]
+    assert len(sched) >= 2
     assert any(c["chunk"] == chosen["chunk"] and c["pair_tile"] == chosen["pair_tile"]
-               and c["persistent"] == chosen["persistent"] for c in cands)
+               and c["persistent"] == chosen["persistent"] for c in sched)
+    # kernel shape (pairs per workgroup of the 8x8 .. 2x2 stages) timed under
+    # the chosen schedule; the faster one is kept
+    assert sorted(c["wg_pairs_mult"] for c in shape) == [1, 2]
+    assert all(c["chunk"] == chosen["chunk"] and c["pair_tile"] == chosen["pair_tile"]
+               and c["persistent"] == chosen["persistent"] for c in shape)
+    assert chosen["wg_pairs_mult"] == min(shape, key=lambda c: c["us_per_pair"])["wg_pairs_mult"]
+
+
+@pytest.mark.parametrize("mult", [2, 1])
+def test_batched_kernel_shapes_are_bitwise_equal(nk, mult):
+    """Both kernel shapes of the stages of tiles of at most 16 x 16 (one or
+    two pairs-per-workgroup multiples), fixed through
+    nk_myrtle_batched_set_schedule, give the one-block entry point's values
+    bit for bit, on uneven tiles with symmetric ones among them."""
+    depth = (1, 2, 2)  # a network no other test tunes
+    xa = _gpu(synth.correlated_images(40, 16, 16, 3, 2.0, 31))
+    xb = _gpu(synth.correlated_images(33, 16, 16, 3, 2.0, 32))
+    tiles = _tiles_from_shapes(xa, xb, [(40, 33), (9, 31), (25, 25), (40, 1), (3, 3), (17, 2)], sym_every=2, pad=3)
+    nk.batched_set_schedule(16, 3, depth, chunk=512, pair_tile=8, persistent=1, wg_pairs_mult=mult)
+    _say(f"batched 16x16 Myrtle-7, pairs-per-workgroup multiple {mult}")
+    nk.myrtle_nngp_batched(tiles, depth)
+    torch.cuda.synchronize()
+    for t, (x1, x2, out) in enumerate(tiles):
+        n2 = x1.shape[0] if x2 is None else x2.shape[0]
+        ref = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+        got = out[:, :n2].cpu().numpy()
+        assert np.array_equal(got, ref), f"tile {t} differs from the one-block entry point"
+        assert torch.isnan(out[:, n2:]).all(), f"tile {t} wrote past n2"
+    cands, chosen = nk.batched_tuning(16, 3, depth)
+    assert cands == [] and chosen["wg_pairs_mult"] == mult
 
 
 def test_batched_graph_replays_match_eager(nk):
