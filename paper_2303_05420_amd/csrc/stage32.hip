@@ -32,10 +32,14 @@
 // (rows twice so that rows r + ky are read without wrapping; each row split
 // into its even columns 0, 2, ..., 32 -- column 32 repeating column 0 -- and
 // its odd columns 1, ..., 31, so that the 16 lanes of a segment read 16
-// consecutive words whichever parity their column jx starts at); the pooling
-// row [16][16][16] float; first stage only: x1 pixels [32][32] float4 (each
-// row split into even and odd columns) and x2 pixels [64][33] float4 (as the
-// x2 tables).  Plain row-major rows would put the lanes of a segment 16 or
+// consecutive words whichever parity their column jx starts at); the x-pool
+// exchange [2][2][8][16 x 16] float (s32_emit); first stage only: x1 pixels
+// [32][32] float4 (each row split into even and odd columns) and x2 pixels
+// [64][33] float4 (as the x2 tables).  The x part of the pool needs no
+// workgroup barrier: a coarse column is summed inside one wave but for one
+// term from the wave before, passed through LDS under per-wave flags (one
+// barrier per coarse row, even a single one, cost 5 % here: the waves'
+// drift over two ky steps).  Plain row-major rows would put the lanes of a segment 16 or
 // 32 bytes apart and cost LDS bank conflicts.
 #include "stage_kernel.h"
 
@@ -47,9 +51,14 @@ constexpr int kN = 32, kH = 16, kThreads = 512, kP = 33;  // kP: padded row of t
 
 __host__ __device__ constexpr size_t s32_t1_bytes(int D) { return (size_t)D * kN * kN * 8; }
 __host__ __device__ constexpr size_t s32_t2_bytes(int D) { return (size_t)D * 2 * kN * kP * 8; }
-__host__ __device__ constexpr size_t s32_red_bytes() { return (size_t)kH * kH * kH * 4; }
+// x-pool exchange (emit without a workgroup barrier): per buffer (two, by
+// parity of the emit), per wave, a 16 x 16 block of the coarse row for
+// `part` (one coarse column less its cross-wave third) and one for `carry`
+// (that third, for the next wave), laid out [I / 4][lane][4].
+constexpr int kWaves = kThreads / 64;
+__host__ __device__ constexpr size_t s32_xfer_bytes() { return (size_t)2 * 2 * kWaves * kH * kH * 4; }
 __host__ __device__ constexpr size_t s32_lds_bytes(int D, bool seed) {
-  return s32_t1_bytes(D) + s32_t2_bytes(D) + s32_red_bytes() +
+  return s32_t1_bytes(D) + s32_t2_bytes(D) + s32_xfer_bytes() +
          (seed ? (size_t)kN * kN * 16 + (size_t)2 * kN * kP * 16 : 0);
 }
 
@@ -161,7 +170,10 @@ __device__ __forceinline__ void layer2(float (&A0)[kN], float (&A1)[kN], const f
 struct S32Ctx {
   const float2* t1;   // x1 tables
   const float2* t2;   // x2 tables (padded rows, twice)
-  float* red;         // pooling row
+  float* xfer;        // x-pool exchange: [part, carry][buffer][wave][16 x 16]
+  int* fprod;         // per wave: last emit whose part and carry it has written
+  int* fcons;         // per wave: last emit whose carry (of the wave before) it has taken
+  int* abort;         // a wait ran out (set only by a broken protocol): outputs become NaN
   const float4* img1;
   const float4* img2;
   int D, l16, seg, ix0;
@@ -170,10 +182,112 @@ struct S32Ctx {
   const float* inp;   // stage input of this pair (non-seed stages)
 };
 
+// Waits until *f >= v.  The loop is wave-uniform (one LDS word); a wait that
+// runs out (only a broken protocol could make one) sets *abort, after which
+// no wait blocks and the workgroup's outputs are NaN.
+__device__ __forceinline__ void s32_wait(const int* f, int v, int* abort) {
+  int n = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v) {
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (++n == (1 << 20)) {
+      __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      break;
+    }
+  }
+  asm volatile("" ::: "memory");
+}
+
+// Makes this wave's earlier LDS writes (or reads) complete, then sets *f = v.
+__device__ __forceinline__ void s32_publish(int* f, int v) {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The x part of the pool for coarse row Ky, without a workgroup barrier.
+// Wave w holds tile columns kx = 4w + q in its four 16-lane rows q; coarse
+// column Kx takes both columns of kx = 2 Kx, column ix0 (acc0) of 2 Kx + 1 and
+// column ix1 (acc1) of 2 Kx - 1.  So coarse column 2w + 1 lies inside the wave
+// (rows 2, 3 and the acc1 of row 1) and is summed in row 3 with two lane
+// swaps and written at once; coarse column 2w lacks the acc1 of row 3 of
+// wave w - 1: row 1 leaves its sum (`part`) in LDS, row 3 leaves its acc1
+// (`carry`) for wave w + 1, and the column is completed one emit later
+// (s32_consume).  The sums are formed in the order of a plain
+// ((both + acc0) + acc1).  Buffers alternate by emit parity; before reusing
+// one, a wave waits until wave w + 1 has taken its carry from two emits ago.
+__device__ __forceinline__ void s32_emit(const StageArgs& args, const S32Ctx& c, const float (&acc0)[kH],
+                                         const float (&acc1)[kH], int Ky, int E, bool valid, int64_t pl) {
+  const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3;
+  const int b = E & 1;
+  float4* part = reinterpret_cast<float4*>(c.xfer) + ((0 * 2 + b) * kWaves + w) * (kH * kH / 4);
+  float4* carry = reinterpret_cast<float4*>(c.xfer) + ((1 * 2 + b) * kWaves + w) * (kH * kH / 4);
+  if (E > 2) s32_wait(&c.fcons[(w + 1) & (kWaves - 1)], E - 2, c.abort);
+  float res[kH];
+  const float m3 = q == 3 ? 1.f : 0.f;
+#pragma unroll
+  for (int I = 0; I < kH; ++I) {
+    const float u = acc0[I] + acc1[I];
+    // rows 1 and 3 receive u of rows 0 and 2
+    const auto pu = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, u), __builtin_bit_cast(unsigned, u),
+                                                     false, false);
+    // rows 2 and 3 receive acc1 of rows 0 and 1
+    const auto pa = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, acc1[I]),
+                                                     __builtin_bit_cast(unsigned, acc1[I]), false, false);
+    res[I] = __builtin_fmaf(m3, __builtin_bit_cast(float, pa[0]), __builtin_bit_cast(float, pu[0]) + acc0[I]);
+  }
+  if (q == 1) {
+#pragma unroll
+    for (int k = 0; k < kH / 4; ++k)
+      part[k * kH + c.l16] = make_float4(res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3]);
+  } else if (q == 3) {
+#pragma unroll
+    for (int k = 0; k < kH / 4; ++k)
+      carry[k * kH + c.l16] = make_float4(acc1[4 * k], acc1[4 * k + 1], acc1[4 * k + 2], acc1[4 * k + 3]);
+  }
+  s32_publish(&c.fprod[w], E);
+  if (q == 3 && valid) {
+    const bool bad = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+    float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w + 1) * kH * kH + c.l16;
+#pragma unroll
+    for (int I = 0; I < kH; ++I) o[I * kH] = bad ? __builtin_nanf("") : res[I];
+  }
+}
+
+// Completes coarse column 2w of coarse row Ky (emit E): this wave's part
+// plus the carry of wave w - 1, then frees the carry buffer.
+__device__ __forceinline__ void s32_consume(const StageArgs& args, const S32Ctx& c, int Ky, int E, bool valid,
+                                            int64_t pl) {
+  const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3;
+  const int wp = (w + kWaves - 1) & (kWaves - 1);
+  const int b = E & 1;
+  const float4* part = reinterpret_cast<const float4*>(c.xfer) + ((0 * 2 + b) * kWaves + w) * (kH * kH / 4);
+  const float4* carry = reinterpret_cast<const float4*>(c.xfer) + ((1 * 2 + b) * kWaves + wp) * (kH * kH / 4);
+  s32_wait(&c.fprod[wp], E, c.abort);
+  if (q == 1) {
+    float res[kH];
+#pragma unroll
+    for (int k = 0; k < kH / 4; ++k) {
+      const float4 p = part[k * kH + c.l16], r = carry[k * kH + c.l16];
+      res[4 * k] = p.x + r.x;
+      res[4 * k + 1] = p.y + r.y;
+      res[4 * k + 2] = p.z + r.z;
+      res[4 * k + 3] = p.w + r.w;
+    }
+    if (valid) {
+      const bool bad = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+      float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w) * kH * kH + c.l16;
+#pragma unroll
+      for (int I = 0; I < kH; ++I) o[I * kH] = bad ? __builtin_nanf("") : res[I];
+    }
+  }
+  s32_publish(&c.fcons[w], E);
+}
+
 // One ky step: the tile's layers, the y part of the pool, and on the steps
-// that complete a coarse row the x part through LDS and the write of that row.
+// that complete a coarse row (E: that emit's number, counted over the
+// workgroup's life from 1) the x part and the write of that row.
 template <int PAR, bool SEED, bool BIAS, bool C4>
-__device__ __forceinline__ void s32_step(const StageArgs& args, const S32Ctx& c, int ky, float (&acc0)[kH],
+__device__ __forceinline__ void s32_step(const StageArgs& args, const S32Ctx& c, int ky, int E, float (&acc0)[kH],
                                          float (&acc1)[kH], float (&wrap0)[kH], float (&wrap1)[kH], bool valid,
                                          int64_t pl) {
   const int seam = ky == 0 ? -1 : kN - ky;
@@ -259,32 +373,7 @@ __device__ __forceinline__ void s32_step(const StageArgs& args, const S32Ctx& c,
     }
   }
   if (!emit) return;
-  // x part: coarse column l of coarse tile Kx gets both columns of lane l of
-  // kx = 2 Kx, column ix0 of kx = 2 Kx + 1 and column ix1 of kx = 2 Kx - 1
-  float* red = c.red;
-  if (!(kx & 1)) {
-#pragma unroll
-    for (int I = 0; I < kH; ++I) red[((kx >> 1) * kH + I) * kH + c.l16] = acc0[I] + acc1[I];
-  }
-  __syncthreads();
-  if (kx & 1) {
-#pragma unroll
-    for (int I = 0; I < kH; ++I) red[((kx >> 1) * kH + I) * kH + c.l16] += acc0[I];
-  }
-  __syncthreads();
-  if (kx & 1) {
-    const int Kx = ((kx + 1) >> 1) & (kH - 1);
-#pragma unroll
-    for (int I = 0; I < kH; ++I) red[(Kx * kH + I) * kH + c.l16] += acc1[I];
-  }
-  __syncthreads();
-  if (valid) {
-    const int Ky = ky == 0 ? 0 : (ky - 1) >> 1;
-    float4* o = reinterpret_cast<float4*>(args.out + pl * (int64_t)kH * kH * kH * kH + (int64_t)Ky * kH * kH * kH);
-    const float4* rs = reinterpret_cast<const float4*>(red);
-    for (int e = threadIdx.x; e < kH * kH * kH / 4; e += kThreads) o[e] = rs[e];
-  }
-  __syncthreads();
+  s32_emit(args, c, acc0, acc1, ky == 0 ? 0 : (ky - 1) >> 1, E, valid, pl);
   if (ky != 0) {
 #pragma unroll
     for (int I = 0; I < kH; ++I) {
@@ -302,6 +391,7 @@ __global__ __launch_bounds__(kThreads) void stage32_kernel(const StageArgs args)
   __shared__ const float* s_x2;
   __shared__ float* s_k;
   __shared__ int s_same;
+  __shared__ int s_fprod[kWaves], s_fcons[kWaves], s_abort;
 
   const int tid = threadIdx.x;
   S32Ctx c;
@@ -320,8 +410,16 @@ __global__ __launch_bounds__(kThreads) void stage32_kernel(const StageArgs args)
   char* base = smem;
   c.t1 = reinterpret_cast<const float2*>(base);
   c.t2 = reinterpret_cast<const float2*>(base + s32_t1_bytes(c.D));
-  c.red = reinterpret_cast<float*>(base + s32_t1_bytes(c.D) + s32_t2_bytes(c.D));
-  c.img1 = reinterpret_cast<const float4*>(base + s32_t1_bytes(c.D) + s32_t2_bytes(c.D) + s32_red_bytes());
+  c.xfer = reinterpret_cast<float*>(base + s32_t1_bytes(c.D) + s32_t2_bytes(c.D));
+  c.fprod = s_fprod;
+  c.fcons = s_fcons;
+  c.abort = &s_abort;
+  if (tid < kWaves) {
+    s_fprod[tid] = 0;
+    s_fcons[tid] = 0;
+    if (tid == 0) s_abort = 0;
+  }
+  c.img1 = reinterpret_cast<const float4*>(base + s32_t1_bytes(c.D) + s32_t2_bytes(c.D) + s32_xfer_bytes());
   c.img2 = c.img1 + kN * kN;
   float2* t1w = reinterpret_cast<float2*>(base);
   float2* t2w = reinterpret_cast<float2*>(base + s32_t1_bytes(c.D));
@@ -329,6 +427,7 @@ __global__ __launch_bounds__(kThreads) void stage32_kernel(const StageArgs args)
   float4* i2w = const_cast<float4*>(c.img2);
 
   const int64_t nunits = args.np;
+  int E0 = 0;  // emits of the units before this one
   int64_t unit, ustep, uend;
   unit_range(nunits, args.persist, &unit, &ustep, &uend);
   for (; unit < uend; unit += ustep) {
@@ -387,12 +486,19 @@ __global__ __launch_bounds__(kThreads) void stage32_kernel(const StageArgs args)
     float acc0[kH], acc1[kH], wrap0[kH], wrap1[kH];
 #pragma unroll
     for (int I = 0; I < kH; ++I) acc0[I] = acc1[I] = wrap0[I] = wrap1[I] = 0.f;
-    // ky = 1, 2, ..., 31, 0 in pairs (odd ky: seam row 32 - ky odd; even ky: even or none)
+    // ky = 1, 2, ..., 31, 0 in pairs (odd ky: seam row 32 - ky odd; even ky:
+    // even or none).  Emits: ky = 2t + 1 (t >= 1) is emit E0 + t of coarse
+    // row t, ky = 0 emit E0 + 16 of coarse row 0; each is completed after
+    // the next one.
 #pragma unroll 1
     for (int t = 0; t < kN / 2; ++t) {
-      s32_step<1, SEED, BIAS, C4>(args, c, 2 * t + 1, acc0, acc1, wrap0, wrap1, valid, pl);
-      s32_step<0, SEED, BIAS, C4>(args, c, (2 * t + 2) & (kN - 1), acc0, acc1, wrap0, wrap1, valid, pl);
+      s32_step<1, SEED, BIAS, C4>(args, c, 2 * t + 1, E0 + t, acc0, acc1, wrap0, wrap1, valid, pl);
+      if (t >= 2) s32_consume(args, c, t - 1, E0 + t - 1, valid, pl);
+      s32_step<0, SEED, BIAS, C4>(args, c, (2 * t + 2) & (kN - 1), E0 + kH, acc0, acc1, wrap0, wrap1, valid, pl);
     }
+    s32_consume(args, c, kH - 1, E0 + kH - 1, valid, pl);
+    s32_consume(args, c, 0, E0 + kH, valid, pl);
+    E0 += kH;
     __syncthreads();  // LDS is reused by the next unit
   }
 }
