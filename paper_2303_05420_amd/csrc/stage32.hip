@@ -52,11 +52,16 @@ constexpr int kN = 32, kH = 16, kThreads = 512, kP = 33;  // kP: padded row of t
 __host__ __device__ constexpr size_t s32_t1_bytes(int D) { return (size_t)D * kN * kN * 8; }
 __host__ __device__ constexpr size_t s32_t2_bytes(int D) { return (size_t)D * 2 * kN * kP * 8; }
 // x-pool exchange (emit without a workgroup barrier): per buffer (two, by
-// parity of the emit), per wave, a 16 x 16 block of the coarse row for
-// `part` (one coarse column less its cross-wave third) and one for `carry`
-// (that third, for the next wave), laid out [I / 4][lane][4].
+// parity of the emit), per wave, a 16 x 16 block [I][lane] of the coarse row
+// for `part` (one coarse column less its cross-wave third) and one for
+// `carry` (that third, for the next wave); then per wave a [8][16] staging
+// block through which 16-lane rows of results leave as float4 stores of
+// whole waves.
 constexpr int kWaves = kThreads / 64;
-__host__ __device__ constexpr size_t s32_xfer_bytes() { return (size_t)2 * 2 * kWaves * kH * kH * 4; }
+constexpr int kStage = 8 * kH;  // floats of one wave's staging block
+__host__ __device__ constexpr size_t s32_xfer_bytes() {
+  return (size_t)2 * 2 * kWaves * kH * kH * 4 + (size_t)kWaves * kStage * 4;
+}
 __host__ __device__ constexpr size_t s32_lds_bytes(int D, bool seed) {
   return s32_t1_bytes(D) + s32_t2_bytes(D) + s32_xfer_bytes() +
          (seed ? (size_t)kN * kN * 16 + (size_t)2 * kN * kP * 16 : 0);
@@ -170,7 +175,7 @@ __device__ __forceinline__ void layer2(float (&A0)[kN], float (&A1)[kN], const f
 struct S32Ctx {
   const float2* t1;   // x1 tables
   const float2* t2;   // x2 tables (padded rows, twice)
-  float* xfer;        // x-pool exchange: [part, carry][buffer][wave][16 x 16]
+  float* xfer;        // x-pool exchange: [part, carry][buffer][wave][16 x 16], then [wave][8 x 16] staging
   int* fprod;         // per wave: last emit whose part and carry it has written
   int* fcons;         // per wave: last emit whose carry (of the wave before) it has taken
   int* abort;         // a wait ran out (set only by a broken protocol): outputs become NaN
@@ -217,10 +222,11 @@ __device__ __forceinline__ void s32_publish(int* f, int v) {
 // one, a wave waits until wave w + 1 has taken its carry from two emits ago.
 __device__ __forceinline__ void s32_emit(const StageArgs& args, const S32Ctx& c, const float (&acc0)[kH],
                                          const float (&acc1)[kH], int Ky, int E, bool valid, int64_t pl) {
-  const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3;
+  const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3, lane = threadIdx.x & 63;
   const int b = E & 1;
-  float4* part = reinterpret_cast<float4*>(c.xfer) + ((0 * 2 + b) * kWaves + w) * (kH * kH / 4);
-  float4* carry = reinterpret_cast<float4*>(c.xfer) + ((1 * 2 + b) * kWaves + w) * (kH * kH / 4);
+  float* part = c.xfer + ((0 * 2 + b) * kWaves + w) * (kH * kH);
+  float* carry = c.xfer + ((1 * 2 + b) * kWaves + w) * (kH * kH);
+  float* stage = c.xfer + 2 * 2 * kWaves * (kH * kH) + w * kStage;
   if (E > 2) s32_wait(&c.fcons[(w + 1) & (kWaves - 1)], E - 2, c.abort);
   float res[kH];
   const float m3 = q == 3 ? 1.f : 0.f;
@@ -237,50 +243,50 @@ __device__ __forceinline__ void s32_emit(const StageArgs& args, const S32Ctx& c,
   }
   if (q == 1) {
 #pragma unroll
-    for (int k = 0; k < kH / 4; ++k)
-      part[k * kH + c.l16] = make_float4(res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3]);
+    for (int I = 0; I < kH; ++I) part[I * kH + c.l16] = res[I];
   } else if (q == 3) {
 #pragma unroll
-    for (int k = 0; k < kH / 4; ++k)
-      carry[k * kH + c.l16] = make_float4(acc1[4 * k], acc1[4 * k + 1], acc1[4 * k + 2], acc1[4 * k + 3]);
+    for (int I = 0; I < kH; ++I) carry[I * kH + c.l16] = acc1[I];
   }
   s32_publish(&c.fprod[w], E);
-  if (q == 3 && valid) {
-    const bool bad = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
-    float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w + 1) * kH * kH + c.l16;
+  // coarse column 2w + 1 (row 3) out through the staging block, half a row
+  // of 16 I values at a time, as float4 stores of 32 lanes
+  const bool bad = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+  float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w + 1) * kH * kH;
 #pragma unroll
-    for (int I = 0; I < kH; ++I) o[I * kH] = bad ? __builtin_nanf("") : res[I];
+  for (int h = 0; h < 2; ++h) {
+    if (q == 3) {
+#pragma unroll
+      for (int I = 0; I < kH / 2; ++I) stage[I * kH + c.l16] = res[h * (kH / 2) + I];
+    }
+    asm volatile("" ::: "memory");
+    if (lane < 32) {
+      float4 v = reinterpret_cast<const float4*>(stage)[lane];
+      if (bad) v = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+      if (valid) reinterpret_cast<float4*>(o + h * (kH / 2) * kH)[lane] = v;
+    }
+    asm volatile("" ::: "memory");
   }
 }
 
 // Completes coarse column 2w of coarse row Ky (emit E): this wave's part
-// plus the carry of wave w - 1, then frees the carry buffer.
+// plus the carry of wave w - 1 (one float4 per lane), then frees the carry
+// buffer.
 __device__ __forceinline__ void s32_consume(const StageArgs& args, const S32Ctx& c, int Ky, int E, bool valid,
                                             int64_t pl) {
-  const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wp = (w + kWaves - 1) & (kWaves - 1);
   const int b = E & 1;
-  const float4* part = reinterpret_cast<const float4*>(c.xfer) + ((0 * 2 + b) * kWaves + w) * (kH * kH / 4);
-  const float4* carry = reinterpret_cast<const float4*>(c.xfer) + ((1 * 2 + b) * kWaves + wp) * (kH * kH / 4);
+  const float4* part = reinterpret_cast<const float4*>(c.xfer + ((0 * 2 + b) * kWaves + w) * (kH * kH));
+  const float4* carry = reinterpret_cast<const float4*>(c.xfer + ((1 * 2 + b) * kWaves + wp) * (kH * kH));
   s32_wait(&c.fprod[wp], E, c.abort);
-  if (q == 1) {
-    float res[kH];
-#pragma unroll
-    for (int k = 0; k < kH / 4; ++k) {
-      const float4 p = part[k * kH + c.l16], r = carry[k * kH + c.l16];
-      res[4 * k] = p.x + r.x;
-      res[4 * k + 1] = p.y + r.y;
-      res[4 * k + 2] = p.z + r.z;
-      res[4 * k + 3] = p.w + r.w;
-    }
-    if (valid) {
-      const bool bad = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
-      float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w) * kH * kH + c.l16;
-#pragma unroll
-      for (int I = 0; I < kH; ++I) o[I * kH] = bad ? __builtin_nanf("") : res[I];
-    }
-  }
+  const float4 p = part[lane], r = carry[lane];
   s32_publish(&c.fcons[w], E);
+  float4 v = make_float4(p.x + r.x, p.y + r.y, p.z + r.z, p.w + r.w);
+  if (__hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
+    v = make_float4(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+  float* o = args.out + pl * (int64_t)kH * kH * kH * kH + ((int64_t)Ky * kH + 2 * w) * kH * kH;
+  if (valid) reinterpret_cast<float4*>(o)[lane] = v;
 }
 
 // One ky step: the tile's layers, the y part of the pool, and on the steps
