@@ -221,32 +221,38 @@ __device__ __forceinline__ void s32_publish(int* f, int v) {
 // ((both + acc0) + acc1).  Buffers alternate by emit parity; before reusing
 // one, a wave waits until wave w + 1 has taken its carry from two emits ago.
 __device__ __forceinline__ void s32_emit(const StageArgs& args, const S32Ctx& c, const float (&acc0)[kH],
-                                         const float (&acc1)[kH], int Ky, int E, bool valid, int64_t pl) {
+                                         const float (&acc1)[kH], const float (&dead0)[kN], const float (&dead1)[kN],
+                                         int Ky, int E, bool valid, int64_t pl) {
   const int w = threadIdx.x >> 6, q = (threadIdx.x >> 4) & 3, lane = threadIdx.x & 63;
   const int b = E & 1;
   float* part = c.xfer + ((0 * 2 + b) * kWaves + w) * (kH * kH);
   float* carry = c.xfer + ((1 * 2 + b) * kWaves + w) * (kH * kH);
   float* stage = c.xfer + 2 * 2 * kWaves * (kH * kH) + w * kStage;
   if (E > 2) s32_wait(&c.fcons[(w + 1) & (kWaves - 1)], E - 2, c.abort);
+  // the carry (acc1 of row 3) goes first: the swaps below clobber acc1
+  if (q == 3) {
+#pragma unroll
+    for (int I = 0; I < kH; ++I) carry[I * kH + c.l16] = acc1[I];
+  }
   float res[kH];
   const float m3 = q == 3 ? 1.f : 0.f;
+  // Each swap moves the half it is asked for into the rows that need it; its
+  // other operand is an even fine row of the tile, already pooled and dead
+  // here, and only its first result is used, so no copies are made.
 #pragma unroll
   for (int I = 0; I < kH; ++I) {
     const float u = acc0[I] + acc1[I];
     // rows 1 and 3 receive u of rows 0 and 2
-    const auto pu = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, u), __builtin_bit_cast(unsigned, u),
-                                                     false, false);
+    const auto pu = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, dead0[2 * I]),
+                                                     __builtin_bit_cast(unsigned, u), false, false);
     // rows 2 and 3 receive acc1 of rows 0 and 1
-    const auto pa = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, acc1[I]),
+    const auto pa = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, dead1[2 * I]),
                                                      __builtin_bit_cast(unsigned, acc1[I]), false, false);
     res[I] = __builtin_fmaf(m3, __builtin_bit_cast(float, pa[0]), __builtin_bit_cast(float, pu[0]) + acc0[I]);
   }
   if (q == 1) {
 #pragma unroll
     for (int I = 0; I < kH; ++I) part[I * kH + c.l16] = res[I];
-  } else if (q == 3) {
-#pragma unroll
-    for (int I = 0; I < kH; ++I) carry[I * kH + c.l16] = acc1[I];
   }
   s32_publish(&c.fprod[w], E);
   // coarse column 2w + 1 (row 3) out through the staging block, half a row
@@ -379,7 +385,7 @@ __device__ __forceinline__ void s32_step(const StageArgs& args, const S32Ctx& c,
     }
   }
   if (!emit) return;
-  s32_emit(args, c, acc0, acc1, ky == 0 ? 0 : (ky - 1) >> 1, E, valid, pl);
+  s32_emit(args, c, acc0, acc1, A0, A1, ky == 0 ? 0 : (ky - 1) >> 1, E, valid, pl);
   if (ky != 0) {
 #pragma unroll
     for (int I = 0; I < kH; ++I) {
