@@ -14,7 +14,9 @@ J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
 The adjoint needs dJ1/drho = (pi - t) / pi with t = acos(rho).  For
 rho = 1 - u, t = sqrt(u) G(u) with G analytic on [0, 1] (G(0) = sqrt 2);
 G is fitted by a degree-6 polynomial minimising the maximum absolute error of
-sqrt(u) G(u) / pi (Lawson again); negative rho uses acos(-r) = pi - acos(r).
+sqrt(u) G(u) / pi (Lawson again; 2.8e-8), and by one of degree 4 (1.5e-6)
+for the tangent kernel's forward pass (NK_ACOSD4_C0..C4); negative rho uses
+acos(-r) = pi - acos(r).
 
 Run: python gen_relu_poly.py  (prints the coefficients and the fit errors).
 """
@@ -53,7 +55,7 @@ def main(degree: int = 4, m: int = 4000, prefix: str = "NK_J1_C"):
         print(f"#define {prefix}{k} {float(ck)!r}f")
 
 
-def main_acos(degree: int = 6, m: int = 3000):
+def main_acos(degree: int = 6, m: int = 3000, prefix: str = "NK_ACOS_C"):
     mp.mp.dps = 40
 
     def g(u):
@@ -76,10 +78,11 @@ def main_acos(degree: int = 6, m: int = 3000):
         lw /= lw.sum()
     print(f"max absolute error of dJ1/drho (float64 evaluation): {e.max():.3e}")
     for k, ck in enumerate(c.astype(np.float32)):
-        print(f"#define NK_ACOS_C{k} {float(ck)!r}f")
+        print(f"#define {prefix}{k} {float(ck)!r}f")
 
 
 if __name__ == "__main__":
     main()
     main(3, prefix="NK_J1D3_C")
     main_acos()
+    main_acos(4, prefix="NK_ACOSD4_C")

@@ -36,6 +36,13 @@
 #define NK_ACOS_C4 0.00692177377641201f
 #define NK_ACOS_C5 -0.0036669515538960695f
 #define NK_ACOS_C6 0.0026117281522601843f
+// degree-4 fit of G (absolute error of sqrt(u) G(u) / pi 1.5e-6): the
+// tangent kernel's forward pass
+#define NK_ACOSD4_C0 1.4142640829086304f
+#define NK_ACOSD4_C1 0.11692662537097931f
+#define NK_ACOSD4_C2 0.031181575730443f
+#define NK_ACOSD4_C3 -0.0013137111673131585f
+#define NK_ACOSD4_C4 0.009732994250953197f
 
 #define NK_MAX_STAGES 4
 #define NK_MAX_DEPTH 4
@@ -209,6 +216,17 @@ __device__ __forceinline__ float acos_g_pi(float u) {
   p = __builtin_fmaf(p, u, NK_ACOS_C2 * ip);
   p = __builtin_fmaf(p, u, NK_ACOS_C1 * ip);
   p = __builtin_fmaf(p, u, NK_ACOS_C0 * ip);
+  return p;
+}
+
+// acos_g_pi with the degree-4 fit (the tangent kernel's forward pass).
+__device__ __forceinline__ float acos_g_pi4(float u) {
+  constexpr float ip = 0.31830988618379067f;
+  float p = NK_ACOSD4_C4 * ip;
+  p = __builtin_fmaf(p, u, NK_ACOSD4_C3 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD4_C2 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD4_C1 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD4_C0 * ip);
   return p;
 }
 

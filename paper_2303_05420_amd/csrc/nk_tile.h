@@ -111,7 +111,10 @@ __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restri
 // the rounding of rho (about 1e-7) would move Fdot by about 1e-4 where rho
 // is 1 exactly: on the displacement-0 tile of a pair of identical images
 // (i = j) the caller passes umax = 0, which pins u = 1 - rho to 0 there
-// (umax = 1 elsewhere: the plain clamp).
+// (umax = 1 elsewhere: the plain clamp).  J1 uses the degree-3 fit of H (as
+// the NNGP stages) and acos the degree-4 fit of G (absolute error 1.5e-6 of
+// acos(rho) / pi); the adjoint, which differentiates the map, keeps the
+// degree-4 and degree-6 fits.
 template <int N, bool SIGNED, bool BIAS>
 __device__ __forceinline__ void tile_layer_ntk(float (&A)[N], float (&C)[N], const float2* __restrict__ c1,
                                                const float2* __restrict__ c2, int seam, float mL, float mR,
@@ -147,13 +150,13 @@ __device__ __forceinline__ void tile_layer_ntk(float (&A)[N], float (&C)[N], con
       const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-__builtin_fabsf(v), rr, 1.0f), 0.0f, umax);
       const float cc = __builtin_amdgcn_fmed3f(__builtin_fmaf(v, rr, 1.0f), 0.0f, 1.0f);
       const float sq = __builtin_amdgcn_sqrtf(u);
-      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), cc);
-      th = sq * acos_g_pi(u);
+      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly3(u), 1.0f), cc);
+      th = sq * acos_g_pi4(u);
     } else {
       const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-v, rr, 1.0f), 0.0f, umax);
       const float sq = __builtin_amdgcn_sqrtf(u);
-      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly(u), 1.0f), 1.0f);
-      th = sq * acos_g_pi(u);
+      J = __builtin_fmaf(-u, __builtin_fmaf(-sq, relu_poly3(u), 1.0f), 1.0f);
+      th = sq * acos_g_pi4(u);
     }
     const float kfd = (SIGNED && v < 0.f) ? kh * th : __builtin_fmaf(-th, kh, kh);
     const float an = (a.y * b.y) * J;

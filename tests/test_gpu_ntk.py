@@ -76,9 +76,9 @@ def test_ntk_nngp_agrees_with_nngp_entry_point(nk):
     x2 = synth.correlated_images(11, 16, 16, 3, 2.0, 65)
     th, k = nk.myrtle_ntk(_gpu(x1), _gpu(x2), (2, 1, 1), with_nngp=True)
     k0 = nk.myrtle_nngp(_gpu(x1), _gpu(x2), (2, 1, 1))
-    # same recursion; the NNGP entry point evaluates the ReLU map with the
-    # degree-3 fit (relative error of the map 1.3e-6), the tangent kernel
-    # with the degree-4 fit (1.3e-7), and sums in another order
+    # same recursion and the same degree-3 fit of the ReLU map (relative
+    # error 1.3e-6); the two kernels sum in another order (row pairs, two
+    # columns per lane in the NNGP's 32x32 stage)
     err = float((k - k0).abs().max() / k0.abs().max())
     _say(f"  NNGP of the NTK pass vs the NNGP entry point: {err:.2e}")
     assert err <= 5e-6
