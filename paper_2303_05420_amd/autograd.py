@@ -33,7 +33,8 @@ class MyrtleNNGP(torch.autograd.Function):
     def backward(ctx, gK):
         x1, x2 = ctx.saved_tensors
         dx1, dx2, ds = ops.myrtle_nngp_backward(x1.contiguous(), None if ctx.sym else x2.contiguous(),
-                                                gK.contiguous().float(), ctx.depth, ctx.sw2, ctx.sb2)
+                                                gK.contiguous().float(), ctx.depth, ctx.sw2, ctx.sb2,
+                                                need_dx2=ctx.sym or ctx.needs_input_grad[1])
         gw, gb = (None if like is None else ds[i].to(dtype=like[0], device=like[1])
                   for i, like in enumerate(ctx.sig_like))
         return dx1, None if ctx.sym else dx2, gw, gb, None

@@ -672,9 +672,12 @@ int check_bwd_lds(const NetDesc& net) {
 // reverse and the casts are the caller's).  Per chunk: the forward stages up
 // to the last stage's input (the checkpoints), then the adjoint stages in
 // reverse order.
+// xj: accumulate x2's seed gradients into xb2 (false: not wanted; xb2 may
+// then be null for 32x32 images); dk_t: dK is stored transposed.
 int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym, const float* dK,
               int64_t lddk, const float2* tab1, const float2* tab2, double* W1, double* W2, double* xb1, double* xb2,
-              double* sums, float* const* bufs, float* const* gbufs, int64_t chunk, hipStream_t s) {
+              double* sums, float* const* bufs, float* const* gbufs, int64_t chunk, hipStream_t s, bool xj = true,
+              bool dk_t = false) {
   const int tl = nk::table_len(net);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
@@ -707,6 +710,7 @@ int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, 
       b.gout = st > 0 ? gbufs[st] : nullptr;
       b.dK = dK; b.lddk = lddk; b.last = st + 1 == net.S ? 1 : 0;
       b.W1 = W1; b.W2 = W2; b.xbar1 = xb1; b.xbar2 = xb2; b.sums = sums;
+      b.xj = xj ? 1 : 0; b.dk_t = dk_t ? 1 : 0;
       char nm[48];
       snprintf(nm, sizeof nm, "myrtle_stage%d_n%d_bwd", st + 1, net.hw >> st);
       ProfScope ps(nm, s);
@@ -1269,7 +1273,10 @@ int nk_myrtle_nngp_backward(const float* x1, int64_t n1, const float* x2, int64_
     bufs[st] = at<float>(ws, p.buf[st]);
     gbufs[st] = at<float>(ws, p.gbuf[st]);
   }
-  if ((rc = bwd_block(net, x1, n1, x2, n2, sym, dK, lddk, tab1, tab2, W1, W2, xb1, xb2, sums, bufs, gbufs, chunk, s)))
+  // x2's seed gradients only when asked for (a symmetric block's two sides
+  // are the same images)
+  if ((rc = bwd_block(net, x1, n1, x2, n2, sym, dK, lddk, tab1, tab2, W1, W2, xb1, xb2, sums, bufs, gbufs, chunk, s,
+                      sym || dx2 != nullptr)))
     return rc;
   {
     ProfScope ps("myrtle_self_bwd", s);
@@ -1428,8 +1435,11 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
   if ((rc = bwd_block(net, x_s, n, x_s, n, true, dss, n, tab_s, tab_s, W_s, W_s, xb_s, xb_s, sums, bufs, gbufs, chunk,
                       s)))
     return rc;
-  if ((rc = bwd_block(net, x_t, m, x_s, n, false, dts, n, tab_t, tab_s, W_t, W_s, xb_t, xb_s, sums, bufs, gbufs, chunk,
-                      s)))
+  // the cross block as (support, targets) with its cotangent read transposed:
+  // the support images' seed gradients are then the fixed-frame (i-side)
+  // sums, and the targets' (not wanted) are not accumulated at 32x32
+  if ((rc = bwd_block(net, x_s, n, x_t, m, false, dts, n, tab_s, tab_t, W_s, W_t, xb_s, xb_t, sums, bufs, gbufs, chunk,
+                      s, /*xj=*/false, /*dk_t=*/true)))
     return rc;
   {
     // the self-chain reverse is linear in W: once per image set on the summed

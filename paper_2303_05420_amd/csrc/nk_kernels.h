@@ -99,6 +99,8 @@ struct StageBwdArgs {
   double* W2;
   double* xbar1;      // per image seed gradients [img][N N C] (first stage)
   double* xbar2;
+  int xj;             // 1: accumulate xbar2; 0: x2's seed gradients are not wanted (xbar2 may be null at 32x32)
+  int dk_t;           // 1: dK is stored transposed, dK[x2 row * lddk + x1 row]
   double* sums;       // [0]: sigma_w2 * dL/dsigma_w2 terms, [1]: dL/dsigma_b2 terms
 };
 

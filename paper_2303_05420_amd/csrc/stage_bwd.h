@@ -240,7 +240,10 @@ struct BOcc {
   static constexpr int W = 512 / est < 1 ? 1 : (512 / est > 8 ? 8 : 512 / est);
 };
 
-template <int N, int D, int CC>
+// XJ: accumulate the second image's seed gradients (the j-side sums, which
+// follow the sweep in a rotating frame); without them (args.xj = 0, callers
+// that need no gradient for x2) the lane keeps 48 fewer registers at C = 3.
+template <int N, int D, int CC, bool XJ = true>
 __global__ __launch_bounds__(BCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(BOcc<N, D, CC>::W)))
 void stage_bwd_kernel(const StageBwdArgs args) {
   using B = BCfg<N>;
@@ -249,6 +252,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   constexpr int THREADS = B::THREADS, SPAN = B::SPAN, WPP = B::WPP;
   constexpr int NN = N * N, TL = D * NN, H = N / 2;
   constexpr int DA = D > 0 ? D : 1, CA = CC > 0 ? CC : 1;
+  constexpr int CJ = XJ ? CC : 0, CJA = CJ > 0 ? CJ : 1;  // j-side seed sums kept
   constexpr size_t SLOT = bwd_slot_lds_bytes<N>(D, SEED);
   extern __shared__ __attribute__((aligned(16))) char smem[];
   __shared__ int64_t s_pa[PPWG], s_pb[PPWG];
@@ -327,17 +331,20 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   // the chunk buffers equals what the owning slot writes; its sums are dropped.
   float gpair = 0.f;
   if (last) {
-    gpair = args.dK[pa * args.lddk + pb];
+    // (dk_t: the block's cotangent is stored transposed, [x2 row][x1 row])
+    gpair = args.dk_t ? args.dK[pb * args.lddk + pa] : args.dK[pa * args.lddk + pb];
     if (args.sym && pa != pb) gpair += args.dK[pb * args.lddk + pa];
   }
 
-  float Wi[DA][RPL], Wj[DA][RPL], Xi[CA][RPL], Xj[CA][RPL];
+  float Wi[DA][RPL], Wj[DA][RPL], Xi[CA][RPL], Xj[CJA][RPL];
 #pragma unroll
   for (int rr = 0; rr < RPL; ++rr) {
 #pragma unroll
     for (int l = 0; l < DA; ++l) Wi[l][rr] = Wj[l][rr] = 0.f;
 #pragma unroll
-    for (int c = 0; c < CA; ++c) Xi[c][rr] = Xj[c][rr] = 0.f;
+    for (int c = 0; c < CA; ++c) Xi[c][rr] = 0.f;
+#pragma unroll
+    for (int c = 0; c < CJA; ++c) Xj[c][rr] = 0.f;
   }
   const float sb2 = args.sb2, ssd = args.seed_scale;
   double swd = 0.0, sbd = 0.0;
@@ -350,7 +357,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 #pragma unroll
       for (int l = 0; l < D; ++l) take_lane<RPL>(Wj[l], src);
 #pragma unroll
-      for (int c = 0; c < CC; ++c) take_lane<RPL>(Xj[c], src);
+      for (int c = 0; c < CJ; ++c) take_lane<RPL>(Xj[c], src);
     }
     const float mL = (ix >= 1 && ix != N - kx) ? 1.f : 0.f;
     const float mR = (ix + 1 < N && ix + 1 != N - kx) ? 1.f : 0.f;
@@ -437,7 +444,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 #pragma unroll
           for (int c = 0; c < CC; ++c) {
             Xi[c][rr] = __builtin_fmaf(gb, wc[c], Xi[c][rr]);
-            Xj[c][rr] = __builtin_fmaf(gb, uc[c], Xj[c][rr]);
+            if constexpr (XJ) Xj[c][rr] = __builtin_fmaf(gb, uc[c], Xj[c][rr]);
           }
         }
       } else {
@@ -451,7 +458,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 #pragma unroll
       for (int l = 0; l < D; ++l) rot_rows<N, RS, RPL>(Wj[l], part);
 #pragma unroll
-      for (int c = 0; c < CC; ++c) rot_rows<N, RS, RPL>(Xj[c], part);
+      for (int c = 0; c < CJ; ++c) rot_rows<N, RS, RPL>(Xj[c], part);
     }
   }
   // j-sums back to lane ix <-> pixel column ix (the frame is at the last column)
@@ -460,7 +467,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 #pragma unroll
     for (int l = 0; l < D; ++l) take_lane<RPL>(Wj[l], src);
 #pragma unroll
-    for (int c = 0; c < CC; ++c) take_lane<RPL>(Xj[c], src);
+    for (int c = 0; c < CJ; ++c) take_lane<RPL>(Xj[c], src);
   }
 #pragma unroll
   for (int l = 0; l < D; ++l) {
@@ -468,10 +475,9 @@ void stage_bwd_kernel(const StageBwdArgs args) {
     seg_reduce<N, RPL>(Wj[l]);
   }
 #pragma unroll
-  for (int c = 0; c < CC; ++c) {
-    seg_reduce<N, RPL>(Xi[c]);
-    seg_reduce<N, RPL>(Xj[c]);
-  }
+  for (int c = 0; c < CC; ++c) seg_reduce<N, RPL>(Xi[c]);
+#pragma unroll
+  for (int c = 0; c < CJ; ++c) seg_reduce<N, RPL>(Xj[c]);
   // scalars: wave sums (a slot past the chunk end re-ran a clamped pair and
   // adds nothing; such slots are the last ones of the workgroup)
   if (!valid) {
@@ -505,10 +511,9 @@ void stage_bwd_kernel(const StageBwdArgs args) {
           aw2[l * NN + px] = (w == 0 ? 0.f : aw2[l * NN + px]) + Wj[l][rr];
         }
 #pragma unroll
-        for (int c = 0; c < CC; ++c) {
-          ax1[px * CC + c] = (w == 0 ? 0.f : ax1[px * CC + c]) + Xi[c][rr];
-          ax2[px * CC + c] = (w == 0 ? 0.f : ax2[px * CC + c]) + Xj[c][rr];
-        }
+        for (int c = 0; c < CC; ++c) ax1[px * CC + c] = (w == 0 ? 0.f : ax1[px * CC + c]) + Xi[c][rr];
+#pragma unroll
+        for (int c = 0; c < CJ; ++c) ax2[px * CC + c] = (w == 0 ? 0.f : ax2[px * CC + c]) + Xj[c][rr];
       }
     }
     __syncthreads();
@@ -521,7 +526,7 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   if constexpr (SEED) {
     for (int e = within; e < NN * CC; e += TPP) {
       atomicAdd(&args.xbar1[pa * (int64_t)NN * CC + e], (double)ax1[e]);
-      atomicAdd(&args.xbar2[pb * (int64_t)NN * CC + e], (double)ax2[e]);
+      if constexpr (XJ) atomicAdd(&args.xbar2[pb * (int64_t)NN * CC + e], (double)ax2[e]);
     }
   }
   if (within == 0) {
@@ -530,15 +535,28 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   }
 }
 
-template <int N, int D, int CC>
-int launch_bwd_t(const StageBwdArgs& a, hipStream_t stream) {
+template <int N, int D, int CC, bool XJ>
+int launch_bwd_x(const StageBwdArgs& a, hipStream_t stream) {
   const int64_t nwg = (a.np + BCfg<N>::PPWG - 1) / BCfg<N>::PPWG;
   const size_t lds = (size_t)BCfg<N>::PPWG * bwd_slot_lds_bytes<N>(D, CC > 0);
-  auto fn = stage_bwd_kernel<N, D, CC>;
+  auto fn = stage_bwd_kernel<N, D, CC, XJ>;
   static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
   if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
   hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(BCfg<N>::THREADS), lds, stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// The seed-stage kernel without the second image's seed gradients exists for
+// 32x32 tiles (the adjoint's dominant case); elsewhere they are always
+// accumulated, so xbar2 must then be given.
+template <int N, int D, int CC>
+int launch_bwd_t(const StageBwdArgs& a, hipStream_t stream) {
+  if constexpr (N == 32 && CC > 0) {
+    if (!a.xj) return launch_bwd_x<N, D, CC, false>(a, stream);
+  } else {
+    if (CC > 0 && !a.xj && !a.xbar2) return -2;
+  }
+  return launch_bwd_x<N, D, CC, true>(a, stream);
 }
 
 template <int N, int D>

@@ -167,9 +167,11 @@ def krr_predict(k_train: torch.Tensor, k_test: torch.Tensor, y: torch.Tensor, ri
 
 def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Tensor, depth: Sequence[int],
                          sigma_w2: float = 2.0, sigma_b2: float = 0.0, need_dx: bool = True,
-                         ws: torch.Tensor | None = None):
+                         ws: torch.Tensor | None = None, need_dx2: bool | None = None):
     """Adjoint of myrtle_nngp: returns (dx1, dx2, dsigma[2]) for cotangent dK.
     For x2=None (symmetric block) dx2 is None and dx1 holds the whole gradient.
+    need_dx2=False (default: need_dx) leaves dx2 None and spares the library
+    the second image set's seed gradients.
     An x2 that shares x1's memory (same start, same count) asks for the two
     partial gradients separately, so it is passed as a copy: the library reads
     an aliased pair of arguments as one symmetric block."""
@@ -188,7 +190,9 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
     dK = dK.contiguous()
     cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
     dx1 = torch.empty_like(x1) if need_dx else None
-    dx2 = None if sym or not need_dx else torch.empty_like(x2)
+    if need_dx2 is None:
+        need_dx2 = need_dx
+    dx2 = None if sym or not need_dx2 else torch.empty_like(x2)
     ds = torch.empty(2, dtype=torch.float32, device=x1.device)
     if ws is None:
         need = workspace_size(_lib.NK_OP_MYRTLE_BWD, cfg, n1, n2)

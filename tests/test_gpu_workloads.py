@@ -201,7 +201,26 @@ def test_vjp_identity_cotangent_32x32(nk, two_arrays):
     assert e <= GTOL and np.all(es <= GTOL)
 
 
-@pytest.mark.parametrize("mode", ["x2_none", "x2_is_x1", "distinct"])
+def test_vjp_without_x2_gradient_32x32(nk):
+    """The adjoint without x2's seed gradients (dx2 not asked for; at 32x32 a
+    kernel variant that keeps no j-side image sums) gives the same dx1 and
+    dsigma as the full adjoint, up to float64 summation order."""
+    depth = (2, 1, 1)
+    x1 = _gpu(synth.correlated_images(5, 32, 32, 3, 3.0, 3701))
+    x2 = _gpu(synth.correlated_images(7, 32, 32, 3, 3.0, 3702))
+    g = _gpu(np.random.default_rng(3703).standard_normal((5, 7)).astype(np.float32))
+    _say("vjp 5 x 7 at 32x32 with and without dx2")
+    a1, a2, sa = nk.myrtle_nngp_backward(x1, x2, g, depth, 2.0, 0.02)
+    a1, a2, sa = a1.clone(), a2.clone(), sa.clone()
+    b1, b2, sb = nk.myrtle_nngp_backward(x1, x2, g, depth, 2.0, 0.02, need_dx2=False)
+    assert b2 is None and a2 is not None
+    e = float((a1 - b1).abs().max() / a1.abs().max())
+    es = float(((sa - sb).abs() / sa.abs()).max())
+    _say(f"  dx1 {e:.2e} dsigma {es:.2e}")
+    assert e <= 1e-6 and es <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["x2_none", "x2_is_x1", "distinct", "distinct_x2_fixed"])
 def test_autograd_function(nk, mode):
     """torch.autograd through MyrtleNNGP: gradients of sum(K * G) with respect
     to the images and to both sigmas (given as tensors) against the float64
@@ -212,7 +231,7 @@ def test_autograd_function(nk, mode):
     x1 = synth.correlated_images(3, 8, 8, 3, 2.0, 3501)
     x2 = synth.correlated_images(4, 8, 8, 3, 2.0, 3502)
     t1 = _gpu(x1).requires_grad_(True)
-    t2 = _gpu(x2).requires_grad_(True)
+    t2 = _gpu(x2).requires_grad_(mode != "distinct_x2_fixed")
     sw = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
     sb = torch.tensor(0.03, dtype=torch.float64, requires_grad=True)
     if mode == "x2_none":
@@ -230,6 +249,9 @@ def test_autograd_function(nk, mode):
     if mode == "distinct":
         r1, r2, rs, _ = ograd.myrtle_vjp(x1, x2, pairs, g.ravel().astype(np.float64), depth, 2.0, 0.03)
         assert _rel(t2.grad.cpu().numpy(), r2) <= GTOL
+    elif mode == "distinct_x2_fixed":
+        r1, _, rs, _ = ograd.myrtle_vjp(x1, x2, pairs, g.ravel().astype(np.float64), depth, 2.0, 0.03)
+        assert t2.grad is None
     else:
         r1, _, rs, _ = ograd.myrtle_vjp(x1, None, pairs, g.ravel().astype(np.float64), depth, 2.0, 0.03)
         assert t2.grad is None
@@ -240,16 +262,19 @@ def test_autograd_function(nk, mode):
     assert sw.grad.dtype == torch.float64 and sw.grad.device.type == "cpu"
 
 
-def test_krr_mse_grad_equals_its_parts(nk):
+@pytest.mark.parametrize("hw,ns,nt", [(16, 24, 40), (32, 6, 10)])
+def test_krr_mse_grad_equals_its_parts(nk, hw, ns, nt):
     """nk_krr_mse_grad (one call) against the same step assembled from the
     separate entry points (two blocks, ridge cotangents, two adjoints summed
     on the host): equal up to the float64 summation order of the per-image
-    sums."""
+    sums.  The one call runs the cross block as (support, targets) with its
+    cotangent read transposed and, at 32x32, without the targets' seed
+    gradients; the parts run it as (targets, support) with all sums."""
     w = synth.WORKLOADS["myrtle5_krr_grad"]
     depth = w["depth"]
-    xs = _gpu(synth.correlated_images(24, 16, 16, 3, 2.0, 3601))
-    xt = _gpu(synth.correlated_images(40, 16, 16, 3, 2.0, 3602))
-    ys = _gpu(synth.balanced_labels(24, 10))
+    xs = _gpu(synth.correlated_images(ns, hw, hw, 3, 2.0, 3601))
+    xt = _gpu(synth.correlated_images(nt, hw, hw, 3, 2.0, 3602))
+    ys = _gpu(synth.balanced_labels(ns, 10))
     yt = _gpu(synth.teacher_labels(xt.cpu().numpy(), 10, 3603))
     loss, dx, ds, lam = nk.krr_mse_grad(xs, ys, xt, yt, depth, 2.0, 0.01, 1e-3)
     kss = nk.myrtle_nngp(xs, None, depth, 2.0, 0.01).clone()
