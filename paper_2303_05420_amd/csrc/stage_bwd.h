@@ -406,9 +406,18 @@ void stage_bwd_kernel(const StageBwdArgs args) {
         }
       }
       float sw = 0.f, sb = 0.f;
+      // the stage input, loaded once per tile and kept for the later passes
+      float S[RPL];
 #pragma unroll
       for (int l = D - 1; l >= 0; --l) {
-        load_input(A);
+        if (l == D - 1) {
+          load_input(A);
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) S[rr] = A[rr];
+        } else {
+#pragma unroll
+          for (int rr = 0; rr < RPL; ++rr) A[rr] = S[rr];
+        }
 #pragma unroll
         for (int m = 0; m < l; ++m) {
           const int z = opaque_zero();
