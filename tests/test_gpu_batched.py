@@ -129,6 +129,28 @@ def test_batched_kernel_shapes_are_bitwise_equal(nk, mult):
     assert cands == [] and chosen["wg_pairs_mult"] == mult
 
 
+@pytest.mark.parametrize("persistent", [1, 0])
+def test_batched_32x32_persistent_units_bitwise(nk, persistent):
+    """The 32x32 stage with several pairs per workgroup in a row (persistent
+    grid, 2048-pair chunks over 256 workgroups: about 8 pairs each; the
+    pooling exchange's flags count on from pair to pair) and with one pair
+    per workgroup, against the one-block entry point bit for bit."""
+    depth = (2, 1, 1)  # a network no other test tunes at 32x32
+    xa = _gpu(synth.correlated_images(48, 32, 32, 3, 3.0, 41))
+    xb = _gpu(synth.correlated_images(44, 32, 32, 3, 3.0, 42))
+    tiles = _tiles_from_shapes(xa, xb, [(48, 44), (9, 31), (30, 30), (48, 1), (3, 3), (17, 40)], sym_every=2, pad=2)
+    nk.batched_set_schedule(32, 3, depth, chunk=2048, pair_tile=8, persistent=persistent, wg_pairs_mult=1)
+    _say(f"batched 32x32 Myrtle-5 stage shapes, persistent {persistent}")
+    nk.myrtle_nngp_batched(tiles, depth)
+    torch.cuda.synchronize()
+    for t, (x1, x2, out) in enumerate(tiles):
+        n2 = x1.shape[0] if x2 is None else x2.shape[0]
+        ref = nk.myrtle_nngp(x1, x2, depth).cpu().numpy()
+        got = out[:, :n2].cpu().numpy()
+        assert np.array_equal(got, ref), f"tile {t} differs from the one-block entry point"
+        assert torch.isnan(out[:, n2:]).all(), f"tile {t} wrote past n2"
+
+
 def test_batched_graph_replays_match_eager(nk):
     depth = (2, 2, 2)
     xa = _gpu(synth.correlated_images(48, 16, 16, 3, 2.0, 21))
