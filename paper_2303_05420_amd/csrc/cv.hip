@@ -86,7 +86,8 @@ struct CvB {
 };
 
 // One [3x3 conv, ReLU] layer of a displacement-0 tile (no seam: the
-// vertical links are all present).  The next layer's table float4s of this
+// vertical links are all present), with the forward NNGP's degree-3 fit of
+// the map.  The next layer's table float4s of this
 // thread (src + m * TPS, m < NV) are requested before row RH, so that the
 // registers they land in are live for the rest of the layer only.
 template <int N, bool SIGNED, bool BIAS, int RH, int NV, int TPS, bool FULL>
@@ -117,7 +118,7 @@ __device__ __forceinline__ void cv_layer(float (&A)[N], const float2* __restrict
     const float2 ta = c1[r * N];
     const float2 tb = c2[r * N];
     const float rr = ta.x * tb.x;
-    const float J = SIGNED ? j1_signed_vr(v, rr) : j1_nonneg(v * rr);
+    const float J = SIGNED ? j1_signed_vr3(v, rr) : j1_nonneg3(v * rr);
     A[r] = (ta.y * tb.y) * J;
     hm = h0;
     h0 = hp;
