@@ -34,13 +34,16 @@ namespace nk {
 
 // Workgroup shape of the adjoint.  At N = 32 a tile column is split over two
 // 32-lane halves of a wave (16 rows each); otherwise a segment of N lanes
-// holds whole columns.
-template <int N>
+// holds whole columns.  WIDE (N = 32 only): eight segments of four columns
+// per pair instead of four of eight, so that the one pair's workgroup has two
+// waves on each SIMD (for kernels whose registers fit in 256 per lane).
+template <int N, bool WIDE = false>
 struct BCfg {
+  static_assert(!WIDE || N == 32, "the wide shape is for 32 x 32 tiles");
   static constexpr int RS = (N == 32) ? 2 : 1;   // lane groups a column's rows are split over
   static constexpr int RPL = N / RS;             // rows per lane
   static constexpr int LPS = N * RS;             // lanes per segment
-  static constexpr int SPP = (N == 32) ? 4 : N;  // segments per pair
+  static constexpr int SPP = (N == 32) ? (WIDE ? 8 : 4) : N;  // segments per pair
   static constexpr int CPS = N / SPP;            // tile columns per segment
   static constexpr int TPP = SPP * LPS;          // threads per pair
   static constexpr int THREADS = TPP > 256 ? TPP : 256;
@@ -234,19 +237,26 @@ __device__ __forceinline__ void seg_reduce(float (&A)[RPL]) {
 // RPL (2 + 2 D + 2 CC) (tile, adjoint and the four kinds of sums) plus ~80
 // of addresses and temporaries.  Without this bound the compiler would take
 // a 256-thread workgroup as licence to use all 512 registers for one wave.
-template <int N, int D, int CC>
+// At N = 32 a kernel whose registers fit in 256 (RPL (3 + 2 D + CC + CJ), the
+// above with the kept stage input and only the j-side seed sums it keeps, at
+// most 160) takes the wide shape and two waves per SIMD.
+template <int N, int D, int CC, bool XJ>
 struct BOcc {
+  static constexpr int CJ = XJ ? CC : 0;
+  static constexpr bool WIDE = N == 32 && BCfg<N>::RPL * (3 + 2 * D + CC + CJ) <= 160;
   static constexpr int est = BCfg<N>::RPL * (2 + 2 * D + 2 * CC) + 80;
-  static constexpr int W = 512 / est < 1 ? 1 : (512 / est > 8 ? 8 : 512 / est);
+  static constexpr int W = WIDE ? 2 : (512 / est < 1 ? 1 : (512 / est > 8 ? 8 : 512 / est));
+  static constexpr int THREADS = BCfg<N, WIDE>::THREADS;
 };
 
 // XJ: accumulate the second image's seed gradients (the j-side sums, which
 // follow the sweep in a rotating frame); without them (args.xj = 0, callers
 // that need no gradient for x2) the lane keeps 48 fewer registers at C = 3.
 template <int N, int D, int CC, bool XJ = true>
-__global__ __launch_bounds__(BCfg<N>::THREADS) __attribute__((amdgpu_waves_per_eu(BOcc<N, D, CC>::W)))
+__global__ __launch_bounds__((BOcc<N, D, CC, XJ>::THREADS))
+__attribute__((amdgpu_waves_per_eu(BOcc<N, D, CC, XJ>::W)))
 void stage_bwd_kernel(const StageBwdArgs args) {
-  using B = BCfg<N>;
+  using B = BCfg<N, BOcc<N, D, CC, XJ>::WIDE>;
   constexpr bool SEED = CC > 0;
   constexpr int RS = B::RS, RPL = B::RPL, LPS = B::LPS, CPS = B::CPS, TPP = B::TPP, PPWG = B::PPWG;
   constexpr int THREADS = B::THREADS, SPAN = B::SPAN, WPP = B::WPP;
@@ -546,12 +556,14 @@ void stage_bwd_kernel(const StageBwdArgs args) {
 
 template <int N, int D, int CC, bool XJ>
 int launch_bwd_x(const StageBwdArgs& a, hipStream_t stream) {
-  const int64_t nwg = (a.np + BCfg<N>::PPWG - 1) / BCfg<N>::PPWG;
-  const size_t lds = (size_t)BCfg<N>::PPWG * bwd_slot_lds_bytes<N>(D, CC > 0);
+  using B = BCfg<N, BOcc<N, D, CC, XJ>::WIDE>;
+  static_assert(B::PPWG == BCfg<N>::PPWG, "the LDS size is computed for the narrow shape");
+  const int64_t nwg = (a.np + B::PPWG - 1) / B::PPWG;
+  const size_t lds = (size_t)B::PPWG * bwd_slot_lds_bytes<N>(D, CC > 0);
   auto fn = stage_bwd_kernel<N, D, CC, XJ>;
   static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
   if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
-  hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(BCfg<N>::THREADS), lds, stream, a);
+  hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(B::THREADS), lds, stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
