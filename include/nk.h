@@ -256,6 +256,32 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
 size_t nk_krr_mse_grad_workspace(const nk_myrtle_cfg* cfg, int64_t n, int64_t m, int64_t c);
 
 /*
+ * nk_krr_mse_grad keeping the first stage's output of every pair (the pooled
+ * covariance the second stage reads, (H/2)^4 floats per pair) from the
+ * forward pass for the adjoint instead of re-running the first stage there:
+ * the stage-boundary checkpoints of the recomputation strategy, held for the
+ * whole step (the gradient through the kernel that data distillation, named
+ * in Sec. 1's related work, takes).  The cross block's forward then runs as (support, targets) and is transposed
+ * into K_ts, which can move K_ts, and so the loss and the gradients, by
+ * float32 rounding against nk_krr_mse_grad (the kernel is symmetric in exact
+ * arithmetic).  Arguments as nk_krr_mse_grad; the workspace must hold at
+ * least nk_krr_mse_grad_workspace_keep(cfg, n, m, c) bytes (NK_EINVAL
+ * otherwise).  A one-stage network has nothing to keep and runs as
+ * nk_krr_mse_grad.
+ */
+int nk_krr_mse_grad_kept(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s,
+                         const float* Y_t, int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative,
+                         float* dx_s, float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Workspace bytes for nk_krr_mse_grad_kept: the default workspace plus
+ * (n (n + 1) / 2 + n m) (H/2)^4 floats (about 146 GB at H = 32, n = 256,
+ * m = 2048), less one chunk buffer of the first stage; the same as
+ * nk_krr_mse_grad_workspace for a one-stage network.  0 if the arguments
+ * are invalid. */
+size_t nk_krr_mse_grad_workspace_keep(const nk_myrtle_cfg* cfg, int64_t n, int64_t m, int64_t c);
+
+/*
  * Many Myrtle Gram tiles of uneven size in one scheduled pass (the paper
  * computes a large kernel as many independent blocks, Sec. "Approaches to
  * large-scale kernel methods").  The variance tables of every distinct

@@ -119,6 +119,10 @@ def lib():
     L.nk_krr_mse_grad.restype = ci
     L.nk_krr_mse_grad_workspace.argtypes = [ctypes.POINTER(MyrtleCfg), i64, i64, i64]
     L.nk_krr_mse_grad_workspace.restype = sz
+    L.nk_krr_mse_grad_kept.argtypes = L.nk_krr_mse_grad.argtypes
+    L.nk_krr_mse_grad_kept.restype = ci
+    L.nk_krr_mse_grad_workspace_keep.argtypes = [ctypes.POINTER(MyrtleCfg), i64, i64, i64]
+    L.nk_krr_mse_grad_workspace_keep.restype = sz
     L.nk_myrtle_nngp_batched.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg), P, sz, P, i32]
     L.nk_myrtle_nngp_batched.restype = ci
     L.nk_myrtle_nngp_batched_workspace.argtypes = [ctypes.POINTER(Tile), i32, ctypes.POINTER(MyrtleCfg)]

@@ -390,6 +390,32 @@ int launch_cast_grad(const double* src, float* dst, int64_t n, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// out (cols x rows, dense) = in^T (rows x cols, dense), through a 32 x 33
+// LDS tile so that both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void transpose_f32_kernel(const float* __restrict__ in, int64_t rows, int64_t cols,
+                                                            float* __restrict__ out) {
+  __shared__ float t[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) t[k][tx] = in[r * cols + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) out[c * rows + r] = t[tx][k];
+  }
+}
+
+int launch_transpose_f32(const float* in, int64_t rows, int64_t cols, float* out, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return 0;
+  if ((rows + 31) / 32 > 65535) return -1;
+  hipLaunchKernelGGL(transpose_f32_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)), dim3(256),
+                     0, s, in, rows, cols, out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 int launch_finish_sigma(const double* sums, double sw2, float* dsigma, hipStream_t s) {
   hipLaunchKernelGGL(finish_sigma_kernel, dim3(1), dim3(64), 0, s, sums, sw2, dsigma);
   return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -616,12 +616,24 @@ int64_t max_chunk_ntk(const NetDesc& net, int64_t n1, int64_t n2, bool sym, size
 }
 
 // Myrtle Gram block through the stage kernels (tables already prepared).
+// First-stage output floats of one pair (the pooled covariance that the
+// second stage reads), 0 for a one-stage network.
+int64_t stage1_out_floats(const NetDesc& net) {
+  if (net.S < 2) return 0;
+  const int64_t q = net.hw >> 1;
+  return q * q * q * q;
+}
+
+// keep1 (optional): the first stage's outputs go to keep1 at the pair's
+// position in the block (pair p at keep1 + p * stage1_out_floats) instead of
+// the chunk buffer, so that they outlive the pass.
 int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym,
                      const float2* tab1, const float2* tab2, float* K, int64_t ldk, float* const* bufs,
-                     int64_t chunk, hipStream_t stream) {
+                     int64_t chunk, hipStream_t stream, float* keep1 = nullptr) {
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = std::min(chunk, npairs - p0);
+    float* b1 = keep1 ? keep1 + p0 * stage1_out_floats(net) : bufs[1];
     for (int s = 0; s < net.S; ++s) {
       nk::StageArgs a;
       memset(&a, 0, sizeof a);
@@ -643,8 +655,8 @@ int run_myrtle_pairs(const NetDesc& net, const float* x1, int64_t n1, const floa
       a.seed_scale = net.sw2 / 9.0f / (float)net.C;
       a.img_floats = (int64_t)net.hw * net.hw * net.C;
       const bool pool = s + 1 < net.S;
-      a.in = s > 0 ? bufs[s] : nullptr;
-      a.out = pool ? bufs[s + 1] : nullptr;
+      a.in = s > 0 ? (s == 1 ? b1 : bufs[s]) : nullptr;
+      a.out = pool ? (s == 0 ? b1 : bufs[s + 1]) : nullptr;
       a.K = K;
       a.ldk = ldk;
       char nm[48];
@@ -674,15 +686,19 @@ int check_bwd_lds(const NetDesc& net) {
 // reverse order.
 // xj: accumulate x2's seed gradients into xb2 (false: not wanted; xb2 may
 // then be null for 32x32 images); dk_t: dK is stored transposed.
+// keep1 (optional): the first stage's outputs of the whole block, as
+// run_myrtle_pairs left them for the same (x1, x2, sym); the first stage is
+// then not re-run.
 int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, int64_t n2, bool sym, const float* dK,
               int64_t lddk, const float2* tab1, const float2* tab2, double* W1, double* W2, double* xb1, double* xb2,
               double* sums, float* const* bufs, float* const* gbufs, int64_t chunk, hipStream_t s, bool xj = true,
-              bool dk_t = false) {
+              bool dk_t = false, float* keep1 = nullptr) {
   const int tl = nk::table_len(net);
   const int64_t npairs = nk::pair_count(n1, n2, sym);
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = std::min(chunk, npairs - p0);
-    for (int st = 0; st + 1 < net.S; ++st) {
+    float* b1 = keep1 ? keep1 + p0 * stage1_out_floats(net) : bufs[1];
+    for (int st = keep1 ? 1 : 0; st + 1 < net.S; ++st) {
       nk::StageArgs a;
       memset(&a, 0, sizeof a);
       a.n1 = n1; a.n2 = n2; a.sym = sym ? 1 : 0; a.T = kPairTile; a.p0 = p0; a.np = np;
@@ -690,8 +706,8 @@ int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, 
       a.tablen = tl; a.taboff = nk::table_off(net, st);
       a.C = net.C; a.D = net.depth[st]; a.sb2 = net.sb2; a.seed_scale = net.sw2 / 9.0f / (float)net.C;
       a.img_floats = (int64_t)net.hw * net.hw * net.C;
-      a.in = st > 0 ? bufs[st] : nullptr;
-      a.out = bufs[st + 1];
+      a.in = st > 0 ? (st == 1 ? b1 : bufs[st]) : nullptr;
+      a.out = st == 0 ? b1 : bufs[st + 1];
       char nm[48];
       snprintf(nm, sizeof nm, "myrtle_stage%d_n%d", st + 1, net.hw >> st);
       ProfScope ps(nm, s);
@@ -705,7 +721,7 @@ int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, 
       b.tablen = tl; b.taboff = nk::table_off(net, st);
       b.C = net.C; b.D = net.depth[st]; b.sb2 = net.sb2; b.seed_scale = net.sw2 / 9.0f / (float)net.C;
       b.img_floats = (int64_t)net.hw * net.hw * net.C;
-      b.in = st > 0 ? bufs[st] : nullptr;
+      b.in = st > 0 ? (st == 1 ? b1 : bufs[st]) : nullptr;
       b.gin = st + 1 < net.S ? gbufs[st + 1] : nullptr;
       b.gout = st > 0 ? gbufs[st] : nullptr;
       b.dK = dK; b.lddk = lddk; b.last = st + 1 == net.S ? 1 : 0;
@@ -722,16 +738,21 @@ int bwd_block(const NetDesc& net, const float* x1, int64_t n1, const float* x2, 
 
 // Workspace of nk_krr_mse_grad: both Gram blocks and their cotangents, the
 // tables, adjoint sums and gradients of both image sets, the ridge solve and
-// the chunk buffers (each stage's checkpoint and its adjoint).
+// the chunk buffers (each stage's checkpoint and its adjoint).  keep: the
+// first stage's outputs of every pair of both blocks are kept from the
+// forward pass for the adjoint (keep1) instead of a chunk buffer for them.
 struct KrrGradPlan {
   size_t kss = 0, kts = 0, dss = 0, dts = 0, tab_s = 0, tab_t = 0, scratch = 0, krr = 0, krr_bytes = 0;
   size_t W_s = 0, W_t = 0, xb_s = 0, xb_t = 0, sums = 0, bscratch = 0;
   size_t buf[NK_MAX_STAGES] = {0, 0, 0, 0}, gbuf[NK_MAX_STAGES] = {0, 0, 0, 0};
+  size_t keep1 = 0;
+  bool keep = false;
   size_t total = 0;
 };
 
-KrrGradPlan plan_krr_grad(const NetDesc& net, int64_t n, int64_t m, int64_t c, int64_t chunk) {
+KrrGradPlan plan_krr_grad(const NetDesc& net, int64_t n, int64_t m, int64_t c, int64_t chunk, bool keep = false) {
   KrrGradPlan p;
+  p.keep = keep && net.S > 1;
   Bump b;
   const size_t tl = (size_t)nk::table_len(net);
   const size_t img = (size_t)net.hw * net.hw * net.C;
@@ -754,9 +775,12 @@ KrrGradPlan plan_krr_grad(const NetDesc& net, int64_t n, int64_t m, int64_t c, i
   p.bscratch = b.take((size_t)nk::prep_bwd_scratch_doubles(net) * sizeof(double) * pbb);
   for (int s = 1; s < net.S; ++s) {
     const size_t q = (size_t)(net.hw >> s);
-    p.buf[s] = b.take(q * q * q * q * sizeof(float) * chunk);
+    if (!(p.keep && s == 1)) p.buf[s] = b.take(q * q * q * q * sizeof(float) * chunk);
     p.gbuf[s] = b.take(q * q * q * q * sizeof(float) * chunk);
   }
+  if (p.keep)
+    p.keep1 = b.take((size_t)stage1_out_floats(net) * sizeof(float) *
+                     (size_t)(nk::pair_count(n, n, 1) + nk::pair_count(n, m, 0)));
   p.total = b.off + 256;
   return p;
 }
@@ -1365,9 +1389,20 @@ size_t nk_krr_mse_grad_workspace(const nk_myrtle_cfg* cfg, int64_t n, int64_t m,
   return plan_krr_grad(net, n, m, c, std::min(np, kDefaultChunk)).total;
 }
 
-int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s, const float* Y_t,
-                    int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative, float* dx_s,
-                    float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream) {
+size_t nk_krr_mse_grad_workspace_keep(const nk_myrtle_cfg* cfg, int64_t n, int64_t m, int64_t c) {
+  NetDesc net;
+  if (n <= 0 || m <= 0 || c <= 0 || check_myrtle(cfg, &net)) return 0;
+  const int64_t np = std::max(nk::pair_count(n, n, 1), nk::pair_count(m, n, 0));
+  return plan_krr_grad(net, n, m, c, std::min(np, kDefaultChunk), true).total;
+}
+
+// keep: the first-stage outputs of both blocks stay in the workspace between
+// the passes (nk_krr_mse_grad_kept); otherwise the adjoint pass re-runs the
+// first stage per chunk.
+static int krr_mse_grad_impl(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s,
+                             const float* Y_t, int64_t c, const nk_myrtle_cfg* cfg, double ridge,
+                             int ridge_is_relative, float* dx_s, float* dsigma, double* loss, double* lambda_used,
+                             void* ws, size_t ws_bytes, void* stream, bool keep) {
   NetDesc net;
   int rc = check_myrtle(cfg, &net);
   if (rc) return rc;
@@ -1380,7 +1415,9 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
   if (!ws) return fail(NK_EINVAL, "workspace is NULL");
   const int64_t np = std::max(nk::pair_count(n, n, 1), nk::pair_count(m, n, 0));
   int64_t chunk = std::min(np, kDefaultChunk);
-  KrrGradPlan p = plan_krr_grad(net, n, m, c, chunk);
+  KrrGradPlan p = plan_krr_grad(net, n, m, c, chunk, keep);
+  if (p.keep && ws_bytes < p.total)
+    return fail(NK_EINVAL, "workspace too small to keep the first-stage outputs (need %zu bytes)", p.total);
   if (ws_bytes < p.total) {
     // fewer pairs per pass if the workspace is short of the default
     const size_t fixed = plan_krr_grad(net, n, m, c, 0).total;
@@ -1411,9 +1448,13 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
   float* bufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
   float* gbufs[NK_MAX_STAGES] = {nullptr, nullptr, nullptr, nullptr};
   for (int st = 1; st < net.S; ++st) {
-    bufs[st] = at<float>(ws, p.buf[st]);
+    bufs[st] = p.buf[st] ? at<float>(ws, p.buf[st]) : nullptr;
     gbufs[st] = at<float>(ws, p.gbuf[st]);
   }
+  // kept first-stage outputs: the symmetric block's pairs, then the cross
+  // block's as (support, targets), the order its adjoint runs in
+  float* keep_ss = p.keep ? at<float>(ws, p.keep1) : nullptr;
+  float* keep_st = p.keep ? keep_ss + nk::pair_count(n, n, 1) * stage1_out_floats(net) : nullptr;
   {
     ProfScope ps("myrtle_prepare", s);
     if (nk::launch_prepare(x_s, n, net, tab_s, at<double>(ws, p.scratch), kPrepBlocks, s) ||
@@ -1421,8 +1462,15 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
       return hip_fail("prepare kernel");
   }
   // forward: K_ss (symmetric) and K_ts
-  if ((rc = run_myrtle_pairs(net, x_s, n, x_s, n, true, tab_s, tab_s, kss, n, bufs, chunk, s))) return rc;
-  if ((rc = run_myrtle_pairs(net, x_t, m, x_s, n, false, tab_t, tab_s, kts, n, bufs, chunk, s))) return rc;
+  if ((rc = run_myrtle_pairs(net, x_s, n, x_s, n, true, tab_s, tab_s, kss, n, bufs, chunk, s, keep_ss))) return rc;
+  if (p.keep) {
+    // the cross block as (support, targets), its Gram block (n x m) in the
+    // cotangent's place until it is transposed into K_ts
+    if ((rc = run_myrtle_pairs(net, x_s, n, x_t, m, false, tab_s, tab_t, dts, m, bufs, chunk, s, keep_st))) return rc;
+    if (nk::launch_transpose_f32(dts, n, m, kts, s)) return hip_fail("transpose");
+  } else if ((rc = run_myrtle_pairs(net, x_t, m, x_s, n, false, tab_t, tab_s, kts, n, bufs, chunk, s))) {
+    return rc;
+  }
   // ridge solve, loss and the cotangents of both blocks (synchronises)
   if ((rc = nk_krr_mse_backward(kss, n, kts, m, Y_s, Y_t, c, ridge, ridge_is_relative, dss, dts, loss, lambda_used,
                                 at<char>(ws, p.krr), p.krr_bytes, stream)))
@@ -1433,13 +1481,13 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
       nk::launch_zero_f64(W_t, m * tl, s) || nk::launch_zero_f64(xb_t, m * img, s) || nk::launch_zero_f64(sums, 4, s))
     return hip_fail("zero");
   if ((rc = bwd_block(net, x_s, n, x_s, n, true, dss, n, tab_s, tab_s, W_s, W_s, xb_s, xb_s, sums, bufs, gbufs, chunk,
-                      s)))
+                      s, true, false, keep_ss)))
     return rc;
   // the cross block as (support, targets) with its cotangent read transposed:
   // the support images' seed gradients are then the fixed-frame (i-side)
   // sums, and the targets' (not wanted) are not accumulated at 32x32
   if ((rc = bwd_block(net, x_s, n, x_t, m, false, dts, n, tab_s, tab_t, W_s, W_t, xb_s, xb_t, sums, bufs, gbufs, chunk,
-                      s, /*xj=*/false, /*dk_t=*/true)))
+                      s, /*xj=*/false, /*dk_t=*/true, keep_st)))
     return rc;
   {
     // the self-chain reverse is linear in W: once per image set on the summed
@@ -1453,6 +1501,21 @@ int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, co
   if (dx_s && nk::launch_cast_grad(xb_s, dx_s, n * img, s)) return hip_fail("cast");
   if (dsigma && nk::launch_finish_sigma(sums, (double)net.sw2, dsigma, s)) return hip_fail("sigma");
   return ok();
+}
+
+int nk_krr_mse_grad(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s, const float* Y_t,
+                    int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative, float* dx_s,
+                    float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes, void* stream) {
+  return krr_mse_grad_impl(x_s, n, x_t, m, Y_s, Y_t, c, cfg, ridge, ridge_is_relative, dx_s, dsigma, loss,
+                           lambda_used, ws, ws_bytes, stream, false);
+}
+
+int nk_krr_mse_grad_kept(const float* x_s, int64_t n, const float* x_t, int64_t m, const float* Y_s,
+                         const float* Y_t, int64_t c, const nk_myrtle_cfg* cfg, double ridge, int ridge_is_relative,
+                         float* dx_s, float* dsigma, double* loss, double* lambda_used, void* ws, size_t ws_bytes,
+                         void* stream) {
+  return krr_mse_grad_impl(x_s, n, x_t, m, Y_s, Y_t, c, cfg, ridge, ridge_is_relative, dx_s, dsigma, loss,
+                           lambda_used, ws, ws_bytes, stream, true);
 }
 
 int nk_krr_nystrom(const float* K_nr, int64_t n, int64_t r, int64_t ld_nr, const float* K_rr, int64_t ld_rr,

@@ -160,6 +160,8 @@ int launch_prepare_bwd(const float* x, int64_t n, const NetDesc& net, const doub
                        double* sums, double* scratch, int64_t max_blocks, hipStream_t stream);
 int launch_cast_grad(const double* src, float* dst, int64_t n, hipStream_t s);
 int launch_finish_sigma(const double* sums, double sw2, float* dsigma, hipStream_t s);
+// out (cols x rows) = in^T (rows x cols), both dense; rows <= 65535 * 32.
+int launch_transpose_f32(const float* in, int64_t rows, int64_t cols, float* out, hipStream_t s);
 int launch_zero_f64(double* p, int64_t n, hipStream_t s);
 int launch_cholesky(double* A, int64_t n, int* info, hipStream_t s);
 // In place X (n x c, row-major) <- L^{-1} X (upper = false) or L^{-T} X

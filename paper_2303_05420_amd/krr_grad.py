@@ -19,8 +19,12 @@ from . import ops
 
 def krr_mse_loss_and_grad(x_s: torch.Tensor, y_s: torch.Tensor, x_t: torch.Tensor, y_t: torch.Tensor,
                           depth: Sequence[int], sigma_w2: float, sigma_b2: float, ridge_rel: float = 1e-4,
-                          lam: float | None = None):
-    """Returns (loss, d loss / d x_s, d loss / d[sigma_w2, sigma_b2], lambda)."""
+                          lam: float | None = None, keep_checkpoints: bool = False):
+    """Returns (loss, d loss / d x_s, d loss / d[sigma_w2, sigma_b2], lambda).
+    keep_checkpoints: keep every pair's first-stage output between the forward
+    and the adjoint pass instead of recomputing it (ops.krr_mse_grad)."""
     if lam is None:
-        return ops.krr_mse_grad(x_s, y_s, x_t, y_t, depth, sigma_w2, sigma_b2, ridge_rel, relative=True)
-    return ops.krr_mse_grad(x_s, y_s, x_t, y_t, depth, sigma_w2, sigma_b2, lam, relative=False)
+        return ops.krr_mse_grad(x_s, y_s, x_t, y_t, depth, sigma_w2, sigma_b2, ridge_rel, relative=True,
+                                keep_checkpoints=keep_checkpoints)
+    return ops.krr_mse_grad(x_s, y_s, x_t, y_t, depth, sigma_w2, sigma_b2, lam, relative=False,
+                            keep_checkpoints=keep_checkpoints)

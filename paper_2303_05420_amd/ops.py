@@ -210,11 +210,14 @@ def myrtle_nngp_backward(x1: torch.Tensor, x2: torch.Tensor | None, dK: torch.Te
 
 def krr_mse_grad(x_s: torch.Tensor, y_s: torch.Tensor, x_t: torch.Tensor, y_t: torch.Tensor, depth: Sequence[int],
                  sigma_w2: float = 2.0, sigma_b2: float = 0.0, ridge: float = 1e-4, relative: bool = True,
-                 ws: torch.Tensor | None = None):
+                 ws: torch.Tensor | None = None, keep_checkpoints: bool = False):
     """nk_krr_mse_grad: (loss, dL/dx_s, dL/d[sigma_w2, sigma_b2], lambda) of the
     held-out squared error of kernel ridge regression of the support images
     x_s (labels y_s) onto the targets x_t (labels y_t); lambda = ridge (times
-    mean diag K_ss when relative) is held fixed."""
+    mean diag K_ss when relative) is held fixed.  keep_checkpoints: every
+    pair's first-stage output is kept between the forward and the adjoint
+    pass (nk_krr_mse_grad_kept, nk_krr_mse_grad_workspace_keep bytes of
+    workspace) instead of being recomputed."""
     _check_images(x_s, "x_s")
     _check_images(x_t, "x_t")
     for t, nm in ((y_s, "y_s"), (y_t, "y_t")):
@@ -229,7 +232,8 @@ def krr_mse_grad(x_s: torch.Tensor, y_s: torch.Tensor, x_t: torch.Tensor, y_t: t
         x_t = x_t.clone()
     cfg = _lib.myrtle_cfg(h, c, depth, sigma_w2, sigma_b2)
     if ws is None:
-        need = int(_lib.lib().nk_krr_mse_grad_workspace(ctypes.byref(cfg), n, m, k))
+        size_fn = _lib.lib().nk_krr_mse_grad_workspace_keep if keep_checkpoints else _lib.lib().nk_krr_mse_grad_workspace
+        need = int(size_fn(ctypes.byref(cfg), n, m, k))
         if need == 0:
             raise ValueError("invalid network or sizes for nk_krr_mse_grad")
         ws = workspace(need, x_s.device)
@@ -237,10 +241,10 @@ def krr_mse_grad(x_s: torch.Tensor, y_s: torch.Tensor, x_t: torch.Tensor, y_t: t
     ds = torch.empty(2, dtype=torch.float32, device=x_s.device)
     loss = ctypes.c_double(0.0)
     lam = ctypes.c_double(0.0)
-    rc = _lib.lib().nk_krr_mse_grad(x_s.data_ptr(), n, x_t.data_ptr(), m, y_s.data_ptr(), y_t.data_ptr(), k,
-                                    ctypes.byref(cfg), float(ridge), 1 if relative else 0, dx.data_ptr(),
-                                    ds.data_ptr(), ctypes.byref(loss), ctypes.byref(lam), ws.data_ptr(), ws.numel(),
-                                    _stream(x_s.device))
+    fn = _lib.lib().nk_krr_mse_grad_kept if keep_checkpoints else _lib.lib().nk_krr_mse_grad
+    rc = fn(x_s.data_ptr(), n, x_t.data_ptr(), m, y_s.data_ptr(), y_t.data_ptr(), k, ctypes.byref(cfg), float(ridge),
+            1 if relative else 0, dx.data_ptr(), ds.data_ptr(), ctypes.byref(loss), ctypes.byref(lam), ws.data_ptr(),
+            ws.numel(), _stream(x_s.device))
     _lib.check(rc)
     return loss.value, dx, ds, lam.value
 

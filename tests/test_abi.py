@@ -36,6 +36,36 @@ def test_workspace_size_queries():
     assert L.nk_workspace_size(99, None, 10, 10) == 0
 
 
+def test_krr_grad_keep_workspace():
+    """The workspace that keeps the first-stage outputs between the passes
+    holds (n (n + 1) / 2 + n m) (H/2)^4 floats for them in place of one chunk
+    buffer of that stage (all within the 256-byte alignment of each region);
+    a one-stage network has nothing to keep."""
+    L = _lib.lib()
+    for hw, n, m in ((32, 256, 2048), (16, 24, 40), (8, 5, 7)):
+        cfg = _cfg(hw=hw)
+        base = L.nk_krr_mse_grad_workspace(ctypes.byref(cfg), n, m, 10)
+        keep = L.nk_krr_mse_grad_workspace_keep(ctypes.byref(cfg), n, m, 10)
+        q4 = (hw // 2) ** 4
+        pairs = n * (n + 1) // 2 + n * m
+        chunk = min(max(n * (n + 1) // 2, n * m), 16384)
+        expect = base + 4 * q4 * (pairs - chunk)
+        assert abs(keep - expect) <= 512, (hw, keep, expect)
+    # the kept variant refuses a workspace that only fits the default (no device work)
+    cfg = _cfg(hw=16)
+    base = L.nk_krr_mse_grad_workspace(ctypes.byref(cfg), 24, 40, 10)
+    keep = L.nk_krr_mse_grad_workspace_keep(ctypes.byref(cfg), 24, 40, 10)
+    p, q = ctypes.c_void_p(256), ctypes.c_void_p(512)
+    loss = ctypes.c_double(0.0)
+    assert L.nk_krr_mse_grad_kept(p, 24, q, 40, p, q, 10, ctypes.byref(cfg), 1e-3, 1, p, p, ctypes.byref(loss),
+                                  None, p, keep - 1, None) == _lib.NK_EINVAL
+    assert "keep" in L.nk_last_error().decode() and base < keep
+    one = _cfg(hw=8, depth=(2,))
+    assert (L.nk_krr_mse_grad_workspace_keep(ctypes.byref(one), 5, 7, 10)
+            == L.nk_krr_mse_grad_workspace(ctypes.byref(one), 5, 7, 10) > 0)
+    assert L.nk_krr_mse_grad_workspace_keep(ctypes.byref(_cfg(hw=12)), 5, 7, 10) == 0
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(hw=12), _lib.NK_EUNSUPPORTED),           # not a power of two
     (dict(hw=128), _lib.NK_EUNSUPPORTED),          # above the supported sizes

@@ -262,23 +262,31 @@ def test_autograd_function(nk, mode):
     assert sw.grad.dtype == torch.float64 and sw.grad.device.type == "cpu"
 
 
-@pytest.mark.parametrize("hw,ns,nt", [(16, 24, 40), (32, 6, 10)])
-def test_krr_mse_grad_equals_its_parts(nk, hw, ns, nt):
+@pytest.mark.parametrize("hw,ns,nt,keep", [(16, 24, 40, False), (32, 6, 10, False), (16, 24, 40, True),
+                                           (32, 6, 10, True)])
+def test_krr_mse_grad_equals_its_parts(nk, hw, ns, nt, keep):
     """nk_krr_mse_grad (one call) against the same step assembled from the
     separate entry points (two blocks, ridge cotangents, two adjoints summed
     on the host): equal up to the float64 summation order of the per-image
-    sums.  The one call runs the cross block as (support, targets) with its
-    cotangent read transposed and, at 32x32, without the targets' seed
-    gradients; the parts run it as (targets, support) with all sums."""
+    sums.  The one call runs the cross block's adjoint as (support, targets)
+    with its cotangent read transposed and, at 32x32, without the targets'
+    seed gradients; the parts run it as (targets, support) with all sums.
+    keep: the call keeps the first-stage outputs from its forward pass (its
+    cross block then runs forward as (support, targets) too, transposed into
+    K_ts, so the parts take K_ts from that block)."""
     w = synth.WORKLOADS["myrtle5_krr_grad"]
     depth = w["depth"]
     xs = _gpu(synth.correlated_images(ns, hw, hw, 3, 2.0, 3601))
     xt = _gpu(synth.correlated_images(nt, hw, hw, 3, 2.0, 3602))
     ys = _gpu(synth.balanced_labels(ns, 10))
     yt = _gpu(synth.teacher_labels(xt.cpu().numpy(), 10, 3603))
-    loss, dx, ds, lam = nk.krr_mse_grad(xs, ys, xt, yt, depth, 2.0, 0.01, 1e-3)
+    _say(f"krr_mse_grad at {hw}x{hw}, {ns} support, {nt} targets, kept checkpoints: {keep}")
+    loss, dx, ds, lam = nk.krr_mse_grad(xs, ys, xt, yt, depth, 2.0, 0.01, 1e-3, keep_checkpoints=keep)
     kss = nk.myrtle_nngp(xs, None, depth, 2.0, 0.01).clone()
-    kts = nk.myrtle_nngp(xt, xs, depth, 2.0, 0.01).clone()
+    if keep:
+        kts = nk.myrtle_nngp(xs, xt, depth, 2.0, 0.01).t().contiguous()
+    else:
+        kts = nk.myrtle_nngp(xt, xs, depth, 2.0, 0.01).clone()
     dss, dts, loss2, lam2 = nk.krr_mse_backward(kss, kts, ys, yt, 1e-3, relative=True)
     d1, _, s1 = nk.myrtle_nngp_backward(xs, None, dss, depth, 2.0, 0.01)
     d1, s1 = d1.clone(), s1.clone()
