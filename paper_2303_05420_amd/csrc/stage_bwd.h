@@ -147,8 +147,9 @@ struct RowTables {
   }
 };
 
-// Forward [3x3 conv, ReLU] layer on this lane's rows (recompute).
-template <int N, int RS, int RPL, bool SGN>
+// Forward [3x3 conv, ReLU] layer on this lane's rows (recompute); BIAS:
+// sigma_b2 != 0 (else its add is left out).
+template <int N, int RS, int RPL, bool SGN, bool BIAS>
 __device__ __forceinline__ void bwd_layer_fwd(float (&A)[RPL], const float2* __restrict__ c1,
                                               const float2* __restrict__ c2, int cut, int part, float mL, float mR,
                                               float sb2) {
@@ -157,7 +158,7 @@ __device__ __forceinline__ void bwd_layer_fwd(float (&A)[RPL], const float2* __r
     t.advance(rr);
     const float2 a = t.a[rr];
     const float2 b = t.b[rr];
-    const float rho = (v + sb2) * (a.x * b.x);
+    const float rho = (BIAS ? v + sb2 : v) * (a.x * b.x);
     A[rr] = (a.y * b.y) * (SGN ? j1_signed(rho) : j1_nonneg(rho));
   });
 }
@@ -169,7 +170,7 @@ __device__ __forceinline__ void bwd_layer_fwd(float (&A)[RPL], const float2* __r
 // exactly: on the displacement-0 tile of a pair of identical images the
 // caller passes umax = 0, which pins u = 1 - rho to 0 there (umax = 1
 // elsewhere: the plain clamp).
-template <int N, int RS, int RPL, bool SGN>
+template <int N, int RS, int RPL, bool SGN, bool BIAS>
 __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[RPL], const float2* __restrict__ c1,
                                               const float2* __restrict__ c2, int cut, int part, float mL, float mR,
                                               float sb2, float umax, float (&Wi)[RPL], float (&Wj)[RPL], float& sw,
@@ -180,7 +181,7 @@ __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[
     const float2 a = t.a[rr];
     const float2 b = t.b[rr];
     const float rr_ = a.x * b.x, ss = a.y * b.y;
-    const float rho = (v + sb2) * rr_;
+    const float rho = (BIAS ? v + sb2 : v) * rr_;
     const float arho = SGN ? __builtin_fabsf(rho) : rho;
     const float u = __builtin_amdgcn_fmed3f(1.0f - arho, 0.0f, umax);
     const float sq = __builtin_amdgcn_sqrtf(u);
@@ -252,7 +253,8 @@ struct BOcc {
 // XJ: accumulate the second image's seed gradients (the j-side sums, which
 // follow the sweep in a rotating frame); without them (args.xj = 0, callers
 // that need no gradient for x2) the lane keeps 48 fewer registers at C = 3.
-template <int N, int D, int CC, bool XJ = true>
+// BIAS: sigma_b2 != 0.
+template <int N, int D, int CC, bool XJ, bool BIAS>
 __global__ __launch_bounds__((BOcc<N, D, CC, XJ>::THREADS))
 __attribute__((amdgpu_waves_per_eu(BOcc<N, D, CC, XJ>::W)))
 void stage_bwd_kernel(const StageBwdArgs args) {
@@ -434,36 +436,39 @@ void stage_bwd_kernel(const StageBwdArgs args) {
           const float2* c1 = t1 + z + m * NN + row0 * N + ix;
           const float2* c2 = t2 + z + m * 2 * NN + (ky + row0) * N + jx;
           if (SEED && m == 0)
-            bwd_layer_fwd<N, RS, RPL, true>(A, c1, c2, cut, part, mL, mR, sb2);
+            bwd_layer_fwd<N, RS, RPL, true, BIAS>(A, c1, c2, cut, part, mL, mR, sb2);
           else
-            bwd_layer_fwd<N, RS, RPL, false>(A, c1, c2, cut, part, mL, mR, sb2);
+            bwd_layer_fwd<N, RS, RPL, false, BIAS>(A, c1, c2, cut, part, mL, mR, sb2);
         }
         const int z = opaque_zero();
         const float2* c1 = t1 + z + l * NN + row0 * N + ix;
         const float2* c2 = t2 + z + l * 2 * NN + (ky + row0) * N + jx;
         if (SEED && l == 0)
-          bwd_layer_rev<N, RS, RPL, true>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
+          bwd_layer_rev<N, RS, RPL, true, BIAS>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
         else
-          bwd_layer_rev<N, RS, RPL, false>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
+          bwd_layer_rev<N, RS, RPL, false, BIAS>(A, G, c1, c2, cut, part, mL, mR, sb2, umax, Wi[l], Wj[l], sw, sb);
         bwd_box<N, RS, RPL>(G, cut, part, mL, mR);
       }
-      // G = adjoint of the stage input
+      // G = adjoint of the stage input.  The seed sums are kept without the
+      // seed scale s (applied once after the sweep), and the seed layer's
+      // share of the sigma_w2 sum, sum over tiles of G a0 with
+      // a0 = s <x(i), x'(j)>, is formed after the sweep as well:
+      // s sum_c x_c(i) Xi_c(i), since pixel i of a lane row is fixed.
       if constexpr (SEED) {
         const int z = opaque_zero();
         const float4* im1 = img1 + z + row0 * N + ix;
         const float4* im2 = img2 + z + (row0 + ky) * N + jx;
 #pragma unroll
         for (int rr = 0; rr < RPL; ++rr) {
-          const float4 u = im1[rr * N];
           const float4 w = im2[rr * N];
-          const float a0 = ssd * __builtin_fmaf(u.w, w.w, __builtin_fmaf(u.z, w.z, __builtin_fmaf(u.y, w.y, u.x * w.x)));
-          sw = __builtin_fmaf(G[rr], a0, sw);
-          const float gb = G[rr] * ssd;
-          const float uc[4] = {u.x, u.y, u.z, u.w}, wc[4] = {w.x, w.y, w.z, w.w};
+          const float wc[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-          for (int c = 0; c < CC; ++c) {
-            Xi[c][rr] = __builtin_fmaf(gb, wc[c], Xi[c][rr]);
-            if constexpr (XJ) Xj[c][rr] = __builtin_fmaf(gb, uc[c], Xj[c][rr]);
+          for (int c = 0; c < CC; ++c) Xi[c][rr] = __builtin_fmaf(G[rr], wc[c], Xi[c][rr]);
+          if constexpr (XJ) {
+            const float4 u = im1[rr * N];
+            const float uc[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int c = 0; c < CC; ++c) Xj[c][rr] = __builtin_fmaf(G[rr], uc[c], Xj[c][rr]);
           }
         }
       } else {
@@ -478,6 +483,26 @@ void stage_bwd_kernel(const StageBwdArgs args) {
       for (int l = 0; l < D; ++l) rot_rows<N, RS, RPL>(Wj[l], part);
 #pragma unroll
       for (int c = 0; c < CJ; ++c) rot_rows<N, RS, RPL>(Xj[c], part);
+    }
+  }
+  if constexpr (SEED) {
+    // the seed layer's sigma_w2 share and the seed scale of the seed sums
+    const float4* im1 = img1 + row0 * N + ix;
+    float t = 0.f;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+      const float4 u = im1[rr * N];
+      const float uc[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int c = 0; c < CC; ++c) t = __builtin_fmaf(uc[c], Xi[c][rr], t);
+    }
+    swd += (double)(ssd * t);
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+#pragma unroll
+      for (int c = 0; c < CC; ++c) Xi[c][rr] *= ssd;
+#pragma unroll
+      for (int c = 0; c < CJ; ++c) Xj[c][rr] *= ssd;
     }
   }
   // j-sums back to lane ix <-> pixel column ix (the frame is at the last column)
@@ -554,17 +579,22 @@ void stage_bwd_kernel(const StageBwdArgs args) {
   }
 }
 
-template <int N, int D, int CC, bool XJ>
-int launch_bwd_x(const StageBwdArgs& a, hipStream_t stream) {
+template <int N, int D, int CC, bool XJ, bool BIAS>
+int launch_bwd_xb(const StageBwdArgs& a, hipStream_t stream) {
   using B = BCfg<N, BOcc<N, D, CC, XJ>::WIDE>;
   static_assert(B::PPWG == BCfg<N>::PPWG, "the LDS size is computed for the narrow shape");
   const int64_t nwg = (a.np + B::PPWG - 1) / B::PPWG;
   const size_t lds = (size_t)B::PPWG * bwd_slot_lds_bytes<N>(D, CC > 0);
-  auto fn = stage_bwd_kernel<N, D, CC, XJ>;
+  auto fn = stage_bwd_kernel<N, D, CC, XJ, BIAS>;
   static std::atomic<size_t> seen[kMaxDevices];  // per instantiation
   if (allow_dyn_lds((const void*)fn, lds, seen)) return -3;
   hipLaunchKernelGGL(fn, dim3((unsigned)nwg), dim3(B::THREADS), lds, stream, a);
   return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int N, int D, int CC, bool XJ>
+int launch_bwd_x(const StageBwdArgs& a, hipStream_t stream) {
+  return a.sb2 != 0.f ? launch_bwd_xb<N, D, CC, XJ, true>(a, stream) : launch_bwd_xb<N, D, CC, XJ, false>(a, stream);
 }
 
 // The seed-stage kernel without the second image's seed gradients exists for
