@@ -14,7 +14,8 @@ J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
 The adjoint needs dJ1/drho = (pi - t) / pi with t = acos(rho).  For
 rho = 1 - u, t = sqrt(u) G(u) with G analytic on [0, 1] (G(0) = sqrt 2);
 G is fitted by a degree-6 polynomial minimising the maximum absolute error of
-sqrt(u) G(u) / pi (Lawson again; 2.8e-8), and by one of degree 4 (1.5e-6)
+sqrt(u) G(u) / pi (Lawson again; 2.8e-8), by one of degree 5 (2.0e-7) for
+the adjoint (NK_ACOSD5_C0..C5), and by one of degree 4 (1.5e-6)
 for the tangent kernel's forward pass (NK_ACOSD4_C0..C4); negative rho uses
 acos(-r) = pi - acos(r).
 
@@ -85,4 +86,5 @@ if __name__ == "__main__":
     main()
     main(3, prefix="NK_J1D3_C")
     main_acos()
+    main_acos(5, prefix="NK_ACOSD5_C")
     main_acos(4, prefix="NK_ACOSD4_C")

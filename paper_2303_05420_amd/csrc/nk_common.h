@@ -36,6 +36,14 @@
 #define NK_ACOS_C4 0.00692177377641201f
 #define NK_ACOS_C5 -0.0036669515538960695f
 #define NK_ACOS_C6 0.0026117281522601843f
+// degree-5 fit of G (absolute error of sqrt(u) G(u) / pi 2.0e-7): the
+// adjoint
+#define NK_ACOSD5_C0 1.414205551147461f
+#define NK_ACOSD5_C1 0.11805802583694458f
+#define NK_ACOSD5_C2 0.024997970089316368f
+#define NK_ACOSD5_C3 0.012558783404529095f
+#define NK_ACOSD5_C4 -0.003935873042792082f
+#define NK_ACOSD5_C5 0.00491119921207428f
 // degree-4 fit of G (absolute error of sqrt(u) G(u) / pi 1.5e-6): the
 // tangent kernel's forward pass
 #define NK_ACOSD4_C0 1.4142640829086304f
@@ -216,6 +224,18 @@ __device__ __forceinline__ float acos_g_pi(float u) {
   p = __builtin_fmaf(p, u, NK_ACOS_C2 * ip);
   p = __builtin_fmaf(p, u, NK_ACOS_C1 * ip);
   p = __builtin_fmaf(p, u, NK_ACOS_C0 * ip);
+  return p;
+}
+
+// acos_g_pi with the degree-5 fit (the adjoint).
+__device__ __forceinline__ float acos_g_pi5(float u) {
+  constexpr float ip = 0.31830988618379067f;
+  float p = NK_ACOSD5_C5 * ip;
+  p = __builtin_fmaf(p, u, NK_ACOSD5_C4 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD5_C3 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD5_C2 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD5_C1 * ip);
+  p = __builtin_fmaf(p, u, NK_ACOSD5_C0 * ip);
   return p;
 }
 

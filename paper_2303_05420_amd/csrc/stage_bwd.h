@@ -186,16 +186,16 @@ __device__ __forceinline__ void bwd_layer_rev(const float (&A)[RPL], float (&G)[
     const float u = __builtin_amdgcn_fmed3f(1.0f - arho, 0.0f, umax);
     const float sq = __builtin_amdgcn_sqrtf(u);
     const float J = __builtin_fmaf(u * sq, relu_poly(u), SGN ? __builtin_fmaxf(rho, 0.0f) : rho);
-    const float th = sq * acos_g_pi(u);  // acos(|rho|) / pi
+    const float th = sq * acos_g_pi5(u);  // acos(|rho|) / pi
     const float Jp = (SGN && rho < 0.f) ? th : 1.0f - th;
-    const float out = ss * J;
-    const float gb = G[rr];
-    const float rhob = gb * ss * Jp;
+    // with gs = g beta beta': g out = gs J, rho_bar = gs J', w = gs (J - J' rho)
+    const float gs = G[rr] * ss;
+    const float rhob = gs * Jp;
     const float vb = rhob * rr_;
-    const float w = __builtin_fmaf(gb, out, -rhob * rho);
+    const float w = gs * __builtin_fmaf(-Jp, rho, J);
     Wi[rr] += w;
     Wj[rr] += w;
-    sw = __builtin_fmaf(gb, out, sw);
+    sw = __builtin_fmaf(gs, J, sw);
     sb += vb;
     G[rr] = vb;
   });
