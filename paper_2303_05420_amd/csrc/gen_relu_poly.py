@@ -1,6 +1,7 @@
 """Generates the float32 coefficients of the ReLU arc-cosine map used by the
 HIP kernels (nk_common.h: NK_J1_C0..NK_J1_C4 of the degree-4 fit,
-NK_J1D3_C0..NK_J1D3_C3 of the degree-3 fit, NK_ACOS_C0..NK_ACOS_C6).
+NK_J1D3_C0..NK_J1D3_C3 of the degree-3 fit, NK_ACOSD5_C0..C5 and
+NK_ACOSD4_C0..C4 of the angle).
 
 For cos t = rho in [0, 1] write u = 1 - rho.  The normalised map
 J1(rho) = (sin t + (pi - t) rho) / pi satisfies J1 = rho + u^{3/2} H(u) with H
@@ -13,11 +14,10 @@ J1(rho) = J1(|rho|) - |rho|, so the same polynomial covers [-1, 1].
 
 The adjoint needs dJ1/drho = (pi - t) / pi with t = acos(rho).  For
 rho = 1 - u, t = sqrt(u) G(u) with G analytic on [0, 1] (G(0) = sqrt 2);
-G is fitted by a degree-6 polynomial minimising the maximum absolute error of
-sqrt(u) G(u) / pi (Lawson again; 2.8e-8), by one of degree 5 (2.0e-7) for
-the adjoint (NK_ACOSD5_C0..C5), and by one of degree 4 (1.5e-6)
-for the tangent kernel's forward pass (NK_ACOSD4_C0..C4); negative rho uses
-acos(-r) = pi - acos(r).
+G is fitted by a degree-5 polynomial minimising the maximum absolute error of
+sqrt(u) G(u) / pi (Lawson again; 2.0e-7) for the adjoint (NK_ACOSD5_C0..C5),
+and by one of degree 4 (1.5e-6) for the tangent kernel's forward pass
+(NK_ACOSD4_C0..C4); negative rho uses acos(-r) = pi - acos(r).
 
 Run: python gen_relu_poly.py  (prints the coefficients and the fit errors).
 """
@@ -56,7 +56,7 @@ def main(degree: int = 4, m: int = 4000, prefix: str = "NK_J1_C"):
         print(f"#define {prefix}{k} {float(ck)!r}f")
 
 
-def main_acos(degree: int = 6, m: int = 3000, prefix: str = "NK_ACOS_C"):
+def main_acos(degree: int = 5, m: int = 3000, prefix: str = "NK_ACOSD5_C"):
     mp.mp.dps = 40
 
     def g(u):
@@ -86,5 +86,4 @@ if __name__ == "__main__":
     main()
     main(3, prefix="NK_J1D3_C")
     main_acos()
-    main_acos(5, prefix="NK_ACOSD5_C")
     main_acos(4, prefix="NK_ACOSD4_C")

@@ -27,17 +27,9 @@
 #define NK_J1D3_C2 0.0013594607589766383f
 #define NK_J1D3_C3 0.001435322454199195f
 
-// acos(1 - u) = sqrt(u) G(u); G is our own degree-6 fit on [0, 1]
-// (gen_relu_poly.py; dJ1/drho = 1 - acos(rho)/pi to 2.8e-8).
-#define NK_ACOS_C0 1.414214849472046f
-#define NK_ACOS_C1 0.11780662834644318f
-#define NK_ACOS_C2 0.026962917298078537f
-#define NK_ACOS_C3 0.005945307202637196f
-#define NK_ACOS_C4 0.00692177377641201f
-#define NK_ACOS_C5 -0.0036669515538960695f
-#define NK_ACOS_C6 0.0026117281522601843f
-// degree-5 fit of G (absolute error of sqrt(u) G(u) / pi 2.0e-7): the
-// adjoint
+// acos(1 - u) = sqrt(u) G(u) with G analytic on [0, 1]; G is our own fit
+// (gen_relu_poly.py).  Degree 5 (absolute error of sqrt(u) G(u) / pi
+// 2.0e-7): the adjoint.
 #define NK_ACOSD5_C0 1.414205551147461f
 #define NK_ACOSD5_C1 0.11805802583694458f
 #define NK_ACOSD5_C2 0.024997970089316368f
@@ -213,21 +205,8 @@ __device__ __forceinline__ float j1_signed(float rho) {
   return __builtin_fmaf(u * sq, relu_poly(u), __builtin_fmaxf(rho, 0.0f));
 }
 
-// acos(1 - u) / pi = sqrt(u) G(u) / pi, with 1/pi folded into the
-// coefficients of G.
-__device__ __forceinline__ float acos_g_pi(float u) {
-  constexpr float ip = 0.31830988618379067f;
-  float p = NK_ACOS_C6 * ip;
-  p = __builtin_fmaf(p, u, NK_ACOS_C5 * ip);
-  p = __builtin_fmaf(p, u, NK_ACOS_C4 * ip);
-  p = __builtin_fmaf(p, u, NK_ACOS_C3 * ip);
-  p = __builtin_fmaf(p, u, NK_ACOS_C2 * ip);
-  p = __builtin_fmaf(p, u, NK_ACOS_C1 * ip);
-  p = __builtin_fmaf(p, u, NK_ACOS_C0 * ip);
-  return p;
-}
-
-// acos_g_pi with the degree-5 fit (the adjoint).
+// acos(1 - u) / pi = sqrt(u) G(u) / pi with the degree-5 fit of G (the
+// adjoint), 1/pi folded into its coefficients.
 __device__ __forceinline__ float acos_g_pi5(float u) {
   constexpr float ip = 0.31830988618379067f;
   float p = NK_ACOSD5_C5 * ip;
@@ -239,7 +218,7 @@ __device__ __forceinline__ float acos_g_pi5(float u) {
   return p;
 }
 
-// acos_g_pi with the degree-4 fit (the tangent kernel's forward pass).
+// The same with the degree-4 fit (the tangent kernel's forward pass).
 __device__ __forceinline__ float acos_g_pi4(float u) {
   constexpr float ip = 0.31830988618379067f;
   float p = NK_ACOSD4_C4 * ip;

@@ -114,7 +114,7 @@ __device__ __forceinline__ void tile_layer(float (&A)[N], const float2* __restri
 // (umax = 1 elsewhere: the plain clamp).  J1 uses the degree-3 fit of H (as
 // the NNGP stages) and acos the degree-4 fit of G (absolute error 1.5e-6 of
 // acos(rho) / pi); the adjoint, which differentiates the map, keeps the
-// degree-4 and degree-6 fits.
+// degree-4 fit of H and a degree-5 fit of G.
 template <int N, bool SIGNED, bool BIAS>
 __device__ __forceinline__ void tile_layer_ntk(float (&A)[N], float (&C)[N], const float2* __restrict__ c1,
                                                const float2* __restrict__ c2, int seam, float mL, float mR,

@@ -15,7 +15,8 @@ FLOPS_PER_SEED_ENTRY_PER_CHANNEL = 2
 FLOPS_PER_POOLED_ENTRY = 1
 # Tangent kernel (NTK), on top of the covariance's 30 per entry-layer: the box
 # sum of the tangent (6), the arc-cosine angle from the square root the map
-# already takes (a degree-6 polynomial and one product: 13) and the tangent
+# already takes (counted as a degree-6 polynomial and one product: 13; the
+# kernels evaluate shorter fits of the angle) and the tangent
 # update, derivative factor times tangent plus covariance (2 FMA: 4).  The
 # network's first layer has no tangent input to sum (its tangent is its
 # covariance): 17 there.
