@@ -57,28 +57,30 @@ def test_vjp_block(nk, n1, n2, hw, depth, sb2):
     assert es[0] <= TOL and es[1] <= TOL
 
 
-@pytest.mark.parametrize("depth,C,need_dx2", [
-    ((1, 1, 1), 1, True),    # 512-thread workgroup, j-side seed sums kept
-    ((1, 1, 1), 3, False),   # 512 threads
-    ((2, 1, 1), 1, True),    # 512 threads
-    ((2, 1, 1), 2, False),   # 512 threads
-    ((3, 1, 1), 1, False),   # 512 threads
-    ((3, 1, 1), 3, False),   # 256 threads (registers above 256)
-    ((2, 1, 1), 3, True),    # 256 threads
+@pytest.mark.parametrize("depth,C,need_dx2,sb2", [
+    ((1, 1, 1), 1, True, 0.02),    # 512-thread workgroup, j-side seed sums kept
+    ((1, 1, 1), 3, False, 0.02),   # 512 threads
+    ((2, 1, 1), 1, True, 0.02),    # 512 threads
+    ((2, 1, 1), 2, False, 0.02),   # 512 threads
+    ((3, 1, 1), 1, False, 0.02),   # 512 threads
+    ((3, 1, 1), 3, False, 0.02),   # 256 threads (registers above 256)
+    ((2, 1, 1), 3, True, 0.02),    # 256 threads
+    ((2, 1, 1), 3, False, 0.0),    # 512 threads, the sigma_b2 = 0 variant (the ridge gradient's cross block)
+    ((1, 1, 1), 2, True, 0.0),     # 512 threads, sigma_b2 = 0
 ])
-def test_vjp_32x32_workgroup_shapes(nk, depth, C, need_dx2):
+def test_vjp_32x32_workgroup_shapes(nk, depth, C, need_dx2, sb2):
     """First-stage adjoints at 32x32 in both workgroup shapes (eight
     four-column segments per pair where the registers fit two waves per SIMD,
-    else four of eight), over channel counts and depths, against the float64
-    autograd oracle."""
+    else four of eight), over channel counts, depths and both bias variants,
+    against the float64 autograd oracle."""
     x1 = synth.correlated_images(2, 32, 32, C, 3.0, 1100 + C)
     x2 = synth.correlated_images(2, 32, 32, C, 3.0, 1200 + C)
     gk = np.random.default_rng(7).standard_normal((2, 2)).astype(np.float32)
-    print(f"vjp 2x2 at 32x32 depth {depth} C {C} dx2 {need_dx2}", flush=True)
-    dx1, dx2, ds = nk.myrtle_nngp_backward(_gpu(x1), _gpu(x2), _gpu(gk), depth, 2.0, 0.02, need_dx2=need_dx2)
+    print(f"vjp 2x2 at 32x32 depth {depth} C {C} dx2 {need_dx2} sb2 {sb2}", flush=True)
+    dx1, dx2, ds = nk.myrtle_nngp_backward(_gpu(x1), _gpu(x2), _gpu(gk), depth, 2.0, sb2, need_dx2=need_dx2)
     torch.cuda.synchronize()
     pairs = np.array([[0, 0], [0, 1], [1, 0], [1, 1]])
-    r1, r2, rs, _ = ograd.myrtle_vjp(x1, x2, pairs, gk.ravel().astype(np.float64), depth, 2.0, 0.02)
+    r1, r2, rs, _ = ograd.myrtle_vjp(x1, x2, pairs, gk.ravel().astype(np.float64), depth, 2.0, sb2)
     e1 = _rel(dx1.cpu().numpy(), r1)
     e2 = _rel(dx2.cpu().numpy(), r2) if need_dx2 else 0.0
     es = np.abs(ds.cpu().numpy() - rs) / np.maximum(np.abs(rs), 1e-30)
