@@ -125,7 +125,7 @@ __device__ __forceinline__ void box_rows(const float (&X)[RPL], int cut, int par
 }
 
 // The tables of this lane's rows, each requested two rows before its use:
-// at one wave per SIMD nothing else hides the LDS latency.  (The compiler
+// at one or two waves per SIMD little else hides the LDS latency.  (The compiler
 // barrier keeps each request ahead of the row it runs before.)
 template <int N, int RPL>
 struct RowTables {
