@@ -263,7 +263,9 @@ def test_autograd_function(nk, mode):
 
 
 @pytest.mark.parametrize("hw,ns,nt,keep", [(16, 24, 40, False), (32, 6, 10, False), (16, 24, 40, True),
-                                           (32, 6, 10, True)])
+                                           (32, 6, 10, True),
+                                           # several passes of 16384 pairs in both blocks
+                                           (16, 200, 300, False), (16, 200, 300, True)])
 def test_krr_mse_grad_equals_its_parts(nk, hw, ns, nt, keep):
     """nk_krr_mse_grad (one call) against the same step assembled from the
     separate entry points (two blocks, ridge cotangents, two adjoints summed
@@ -296,10 +298,15 @@ def test_krr_mse_grad_equals_its_parts(nk, hw, ns, nt, keep):
     assert loss == loss2 and lam == lam2
     # the one call sums the two blocks' contributions in float64 and rounds
     # once; the parts are each rounded to float32 first, and they partly
-    # cancel, so the difference is measured against the larger part
+    # cancel, so the difference is measured against the larger part.  The
+    # sigma sums also differ by the order of their float32 per-tile partial
+    # sums (the one call runs the cross block in the other orientation), and
+    # they add terms of both signs over every entry of every pair: at 80,000
+    # pairs that reaches about 1.3e-6 of the larger part, hence 5e-6 there
+    # (half the bar against the float64 oracle).
     scale = max(float(d1.abs().max()), float(d2.abs().max()))
     e = float(np.max(np.abs(dx.cpu().numpy() - ref_dx))) / scale
     sscale = np.maximum(np.abs(s1.double().cpu().numpy()), np.abs(s2.double().cpu().numpy()))
     es = np.abs(ds.cpu().numpy() - ref_ds) / sscale
     _say(f"  one call vs parts: dx {e:.2e} dsigma {es} (relative to the larger part)")
-    assert e <= 1e-6 and np.all(es <= 1e-6)
+    assert e <= 1e-6 and np.all(es <= 5e-6)
