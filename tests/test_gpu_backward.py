@@ -89,6 +89,29 @@ def test_vjp_32x32_workgroup_shapes(nk, depth, C, need_dx2, sb2):
     assert e1 <= TOL and e2 <= TOL and np.all(es <= TOL)
 
 
+@pytest.mark.parametrize("C,sb2", [(2, 0.0), (1, 0.02)])
+def test_vjp_symmetric_32x32_two_waves(nk, C, sb2):
+    """A symmetric 32x32 block (x2 None: self pairs included, their
+    displacement-0 tile at rho = 1 exactly) through a first-stage adjoint that
+    keeps the second image's seed sums and still fits two waves per SIMD
+    (depth 1, one or two channels), cotangent on every entry including the
+    diagonal, against the float64 autograd oracle."""
+    x = synth.correlated_images(3, 32, 32, C, 3.0, 1300 + C)
+    gk = np.random.default_rng(8).standard_normal((3, 3)).astype(np.float32) + 2 * np.eye(3, dtype=np.float32)
+    depth = (1, 1, 1)
+    print(f"vjp symmetric 3x3 at 32x32 C {C} sb2 {sb2}", flush=True)
+    dx, dx2, ds = nk.myrtle_nngp_backward(_gpu(x), None, _gpu(gk), depth, 2.0, sb2)
+    torch.cuda.synchronize()
+    assert dx2 is None
+    a, b = np.meshgrid(np.arange(3), np.arange(3), indexing="ij")
+    pairs = np.stack([a.ravel(), b.ravel()], 1)
+    r, _, rs, _ = ograd.myrtle_vjp(x, None, pairs, gk.ravel().astype(np.float64), depth, 2.0, sb2)
+    e = _rel(dx.cpu().numpy(), r)
+    es = np.abs(ds.cpu().numpy() - rs) / np.maximum(np.abs(rs), 1e-30)
+    print(f"  sym rel err dx {e:.2e} dsigma {es}", flush=True)
+    assert e <= TOL and np.all(es <= TOL)
+
+
 def test_vjp_symmetric(nk):
     x = synth.correlated_images(4, 8, 8, 3, 3.0, 901)
     rng = np.random.default_rng(6)
