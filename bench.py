@@ -463,7 +463,10 @@ def _pcg(torch, cpu: bool):
     fc_launches, fc_ms = _lib.profile_read(reset=True)["fc_nngp"]
     d_in = int(xg.shape[1])
     del xg
-    fc_tflops = 2.0 * n * n * d_in / (fc_ms / 1e3) / 1e12
+    # the block is symmetric: its distinct entries are n (n + 1) / 2, and the
+    # kernel runs the tiles on and above the diagonal and mirrors them
+    fc_flops = 2.0 * d_in * n * (n + 1) / 2
+    fc_tflops = fc_flops / (fc_ms / 1e3) / 1e12
     fc_gram = {"workload": f"FC-3 NNGP Gram of {n} 32x32x3 correlated images (d = {d_in}), {n}x{n}, "
                            f"sigma_w2={w['fc_sigma_w2']}, sigma_b2={w['fc_sigma_b2']}",
                "value": round(n * n / (fc_ms / 1e3), 1), "unit": "entries/s", "ms": round(fc_ms, 3),
@@ -473,7 +476,7 @@ def _pcg(torch, cpu: bool):
                                                        "recursion in its epilogue; the two diagonal kernels "
                                                        "are inside the timed scope)",
                             "avg_launch_ms": round(fc_ms / fc_launches, 3),
-                            "flops_per_launch": 2.0 * n * n * d_in}}
+                            "flops_per_launch": fc_flops}}
     print(f"fc3 gram: {fc_ms:.1f} ms for {n}x{n}", file=sys.stderr, flush=True)
     kt = k.t().contiguous()
     k.add_(kt).mul_(0.5)  # exactly symmetric (the solver reads rows as columns)

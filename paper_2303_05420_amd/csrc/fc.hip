@@ -52,7 +52,10 @@ constexpr int FC_BM = 128, FC_BK = 32, FC_LDR = FC_BK + 4;
 // each XCD has its own L2, so the launch index is first mapped to one
 // contiguous range of tiles per XCD; each range walks the output in groups
 // of FC_GROUP tile rows, column by column, so that the tiles an XCD runs at
-// the same time share few x1 row tiles and x2 column tiles.
+// the same time share few x1 row tiles and x2 column tiles.  A symmetric
+// block (x2 the same images as x1) runs only the tiles on and above the
+// diagonal, in the pair order of the Myrtle stages over tile indices
+// (groups of FC_GROUP), and each off-diagonal tile also writes its mirror.
 constexpr int FC_GROUP = 8;
 
 __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
@@ -60,16 +63,26 @@ __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
   __shared__ __attribute__((aligned(16))) float Bs[FC_BM * FC_LDR];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int64_t r0, c0;
+  bool mirror = false;
   {
     const int64_t gx = gridDim.x, gy = gridDim.y, nb = gx * gy;
     const int64_t lin = (int64_t)blockIdx.y * gx + blockIdx.x;
     const int64_t xcd = lin & 7, q = nb >> 3, rem = nb & 7;
     const int64_t id = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + (lin >> 3);
-    const int64_t grp = id / (FC_GROUP * gx), first = grp * FC_GROUP;
-    const int64_t rows = gy - first < FC_GROUP ? gy - first : FC_GROUP;
-    const int64_t in = id - first * gx;
-    r0 = (first + in % rows) * FC_BM;
-    c0 = (in / rows) * FC_BM;
+    if (a.sym) {
+      const int64_t nt = (a.n1 + FC_BM - 1) / FC_BM;
+      int64_t ti, tj;
+      pair_of(id, nt, nt, 1, FC_GROUP, &ti, &tj);
+      r0 = ti * FC_BM;
+      c0 = tj * FC_BM;
+      mirror = ti != tj;
+    } else {
+      const int64_t grp = id / (FC_GROUP * gx), first = grp * FC_GROUP;
+      const int64_t rows = gy - first < FC_GROUP ? gy - first : FC_GROUP;
+      const int64_t in = id - first * gx;
+      r0 = (first + in % rows) * FC_BM;
+      c0 = (in / rows) * FC_BM;
+    }
   }
   const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
   const int li = lane & 15, ks = lane >> 4;
@@ -124,12 +137,18 @@ __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const int64_t rb = r0 + wr + 16 * i + 4 * ks;  // rows rb .. rb + 3 of this lane
+      const int64_t c = c0 + wc + 16 * j + li;
+      if (c >= a.n2) continue;
+      float kv[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t r = r0 + wr + 16 * i + 4 * ks + v;
-        const int64_t c = c0 + wc + 16 * j + li;
-        if (r >= a.n1 || c >= a.n2) continue;
+        const int64_t r = rb + v;
+        if (r >= a.n1) {
+          kv[v] = 0.f;
+          continue;
+        }
         float k = a.sw2 * acc[i][j][v] * inv_d + a.sb2;
         float q1 = a.d1[r], q2 = a.d2[c];
         for (int l = 0; l < a.depth; ++l) {
@@ -144,8 +163,22 @@ __global__ __launch_bounds__(256) void fc_kernel(const FcArgs a) {
           q1 = 0.5f * a.sw2 * q1 + a.sb2;
           q2 = 0.5f * a.sw2 * q2 + a.sb2;
         }
+        kv[v] = k;
         a.K[r * a.ldk + c] = k;
       }
+      if (mirror) {
+        // row c of the block, columns rb .. rb + 3 (one 16-byte store when
+        // they are in range and aligned)
+        float* m = a.K + c * a.ldk + rb;
+        if (rb + 3 < a.n1 && (reinterpret_cast<uintptr_t>(m) & 15) == 0) {
+          *reinterpret_cast<float4*>(m) = make_float4(kv[0], kv[1], kv[2], kv[3]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (rb + v < a.n1) m[v] = kv[v];
+        }
+      }
+    }
 }
 
 int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream) {
@@ -156,8 +189,13 @@ int launch_fc(const FcArgs& a, float* d1, float* d2, hipStream_t stream) {
   FcArgs b = a;
   b.d1 = d1;
   b.d2 = d2;
-  hipLaunchKernelGGL(fc_kernel, dim3((unsigned)((a.n2 + FC_BM - 1) / FC_BM), (unsigned)((a.n1 + FC_BM - 1) / FC_BM)), dim3(256), 0,
-                     stream, b);
+  const int64_t t1 = (a.n1 + FC_BM - 1) / FC_BM, t2 = (a.n2 + FC_BM - 1) / FC_BM;
+  if (a.sym) {
+    // (the x2 diagonals equal the x1 ones; both are computed, as for any block)
+    hipLaunchKernelGGL(fc_kernel, dim3((unsigned)(t1 * (t1 + 1) / 2)), dim3(256), 0, stream, b);
+  } else {
+    hipLaunchKernelGGL(fc_kernel, dim3((unsigned)t2, (unsigned)t1), dim3(256), 0, stream, b);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

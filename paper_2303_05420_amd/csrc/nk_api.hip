@@ -1110,6 +1110,7 @@ int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const n
   a.d2 = d2;
   a.K = K;
   a.ldk = ldk;
+  a.sym = (x1 == x2 && n1 == n2) ? 1 : 0;
   ProfScope ps("fc_nngp", (hipStream_t)stream);
   if (nk::launch_fc(a, d1, d2, (hipStream_t)stream)) return hip_fail("fc kernel");
   return ok();
@@ -1140,6 +1141,7 @@ int nk_fc_nngp_static(const float* x1, int64_t n1, const float* x2, int64_t n2, 
   a.d2 = d + n1;
   a.K = K;
   a.ldk = ldk;
+  a.sym = (x1 == x2 && n1 == n2) ? 1 : 0;
   if (nk::launch_fc(a, d, d + n1, (hipStream_t)stream)) return hip_fail("fc kernel");
   return ok();
 }

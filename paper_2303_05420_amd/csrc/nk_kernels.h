@@ -126,6 +126,7 @@ struct FcArgs {
   const float* d2;
   float* K;
   int64_t ldk;
+  int sym;  // x1 and x2 are the same images: upper-triangle tiles, mirrored
 };
 
 int64_t prep_scratch_doubles(const NetDesc& net);

@@ -39,6 +39,30 @@ def test_fc3_matches_oracle(nk, n1, n2, hw):
     assert err <= 2e-5
 
 
+@pytest.mark.parametrize("n,hw,pad", [(1, 5, 0), (37, 7, 3), (300, 7, 0), (1100, 16, 5), (1024, 32, 0)])
+def test_fc3_symmetric_block(nk, n, hw, pad):
+    """A symmetric FC-3 block (x2 the same images): the tiles on and above the
+    diagonal run and the others are their mirror, into a row stride padded
+    by `pad` (unaligned rows take the scalar mirror stores); against the
+    float64 oracle and symmetric within float32 rounding."""
+    w = synth.WORKLOADS["fc3_myrtle5_32x32_1024"]
+    x = synth.correlated_images(n, hw, hw, 3, 3.0, w["seeds"][0])
+    print(f"fc3 symmetric {n} x {n} at {hw}x{hw}, ldk {n + pad}", flush=True)
+    big = torch.full((n, n + pad), float("nan"), dtype=torch.float32, device="cuda")
+    out = big[:, :n]
+    nk.fc_nngp(_gpu(x), None, 3, 2.0, 0.01, out=out)
+    torch.cuda.synchronize()
+    kg = out.cpu().numpy()
+    kr = oracle.fc_nngp(x, x, 3, 2.0, 0.01)
+    d = np.sqrt(np.diag(kr))
+    err = np.max(np.abs(kg - kr) / np.outer(d, d))
+    asym = np.max(np.abs(kg - kg.T) / np.outer(d, d))
+    print(f"  normalised error {err:.3e}, asymmetry {asym:.3e}", flush=True)
+    assert err <= 2e-5 and asym <= 1e-6
+    if pad:
+        assert torch.isnan(big[:, n:]).all()  # nothing written past the block
+
+
 def test_krr_predict_matches_oracle(nk):
     w = synth.WORKLOADS["fc3_myrtle5_32x32_1024"]
     x1 = synth.correlated_images(1024, 32, 32, 3, 3.0, w["seeds"][0])
