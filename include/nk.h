@@ -124,7 +124,10 @@ size_t nk_workspace_size(int op, const void* cfg, int64_t n1, int64_t n2);
 
 /*
  * FC NNGP block: K[a, b] = k_FC(x1[a], x2[b]) with x* (n*, d) float32
- * row-major.  The first layer's dot products run on MFMA in fp32.
+ * row-major.  The first layer's dot products run on MFMA in fp32.  x2 == x1
+ * with n2 == n1 is the symmetric block: only the 128 x 128 tiles on and above
+ * the diagonal are computed and the others written as their mirror (K comes
+ * out exactly symmetric).
  */
 int nk_fc_nngp(const float* x1, int64_t n1, const float* x2, int64_t n2, const nk_fc_cfg* cfg, float* K,
                int64_t ldk, void* ws, size_t ws_bytes, void* stream);
